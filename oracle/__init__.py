@@ -1,0 +1,326 @@
+"""FP64 CPU oracle for the normal-deviate path (TEST INFRASTRUCTURE ONLY).
+
+This package wraps ``nrng_oracle.c`` -- a plain single-threaded C99
+implementation, in IEEE double precision without fused multiply-add, of
+Box-Muller Algorithm B1 and the Polar method (Algorithm P) from Section 2 of
+Brent's "Fast Normal Random Number Generators for Vector Processors" (1993),
+fed by a counter-based SplitMix64 uniform stream.
+
+Only the test suite, the smoke check and the CPU-baseline leg of the
+benchmark may import it.  The product library (``paper_1004_3105_amd``)
+never imports, links or calls it, and this package imports nothing from the
+product.  The helpers below only marshal arguments and split long ranges into
+independent chunks (each chunk is one call of the C reference); they do no
+arithmetic of the method themselves.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "nrng_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "libnrng_oracle.so")
+_lock = threading.Lock()
+_lib = None
+
+u64 = ctypes.c_uint64
+i32 = ctypes.c_int32
+f64 = ctypes.c_double
+vp = ctypes.c_void_p
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, no contraction into FMA)."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-std=c99", "-D_DEFAULT_SOURCE", "-ffp-contract=off", "-fno-fast-math",
+               "-fPIC", "-shared", "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def lib():
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+                build(force=True)
+            L = ctypes.CDLL(_LIB_PATH)
+            sig = {
+                "orc_splitmix64": (u64, [u64]),
+                "orc_uniform": (f64, [u64, u64]),
+                "orc_int32": (i32, [u64, u64]),
+                "orc_hash_block": (None, [u64, u64, u64, vp]),
+                "orc_uniform_block": (None, [u64, u64, u64, vp]),
+                "orc_int32_block": (None, [u64, u64, u64, vp]),
+                "orc_b1_uv": (None, [vp, vp, u64, f64, f64, vp]),
+                "orc_b1_words": (None, [vp, u64, f64, f64, vp]),
+                "orc_b1": (u64, [u64, u64, u64, f64, f64, vp]),
+                "orc_polar_accept": (ctypes.c_int, [i32, i32]),
+                "orc_polar_xy": (u64, [vp, u64, f64, f64, vp, vp]),
+                "orc_polar": (u64, [u64, u64, u64, f64, f64, vp]),
+                "orc_polar_count": (u64, [u64, u64, u64]),
+                "orc_polar_trace": (u64, [u64, u64, u64, vp, vp]),
+                "orc_polar_window": (u64, [u64, u64, u64, u64, f64, f64, vp]),
+                "orc_moments": (None, [vp, u64, vp]),
+                "orc_normal_cdf": (f64, [f64]),
+                "orc_ks": (f64, [vp, u64, ctypes.c_int, f64, f64]),
+            }
+            for name, (res, args) in sig.items():
+                fn = getattr(L, name)
+                fn.restype = res
+                fn.argtypes = args
+            _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(vp)
+
+
+M64 = (1 << 64) - 1
+
+
+# ---------------------------------------------------------------- uniforms
+def splitmix64(x: int) -> int:
+    return int(lib().orc_splitmix64(x & M64))
+
+
+def hashes(seed: int, offset: int, count: int) -> np.ndarray:
+    out = np.empty(count, dtype=np.uint64)
+    lib().orc_hash_block(seed & M64, offset & M64, count, _p(out))
+    return out
+
+
+def uniforms(seed: int, offset: int, count: int) -> np.ndarray:
+    out = np.empty(count, dtype=np.float64)
+    lib().orc_uniform_block(seed & M64, offset & M64, count, _p(out))
+    return out
+
+
+def int32s(seed: int, offset: int, count: int) -> np.ndarray:
+    out = np.empty(count, dtype=np.int32)
+    lib().orc_int32_block(seed & M64, offset & M64, count, _p(out))
+    return out
+
+
+# ---------------------------------------------------------------- B1
+def b1(seed: int, offset: int, n: int, mu: float = 0.0, sigma: float = 1.0):
+    """n normals by Algorithm B1; returns (values, uniforms consumed)."""
+    out = np.empty(max(n, 1), dtype=np.float64)
+    used = lib().orc_b1(seed & M64, offset & M64, n, mu, sigma, _p(out))
+    return out[:n], int(used)
+
+
+def b1_uv(u, v, mu: float = 0.0, sigma: float = 1.0) -> np.ndarray:
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    assert u.shape == v.shape
+    out = np.empty(2 * u.size, dtype=np.float64)
+    lib().orc_b1_uv(_p(u), _p(v), u.size, mu, sigma, _p(out))
+    return out
+
+
+def b1_words(words, mu: float = 0.0, sigma: float = 1.0) -> np.ndarray:
+    w = np.ascontiguousarray(words, dtype=np.uint64)
+    assert w.size % 2 == 0
+    out = np.empty(w.size, dtype=np.float64)
+    lib().orc_b1_words(_p(w), w.size // 2, mu, sigma, _p(out))
+    return out
+
+
+def b1_at(seed: int, offset: int, index: np.ndarray, mu: float = 0.0, sigma: float = 1.0) -> np.ndarray:
+    """Values at the given output indices of a B1 stream (each index k is
+    computed on its own from pair k // 2)."""
+    index = np.asarray(index, dtype=np.int64)
+    out = np.empty(index.size, dtype=np.float64)
+    pair = np.empty(2, dtype=np.float64)
+    L = lib()
+    for t, k in enumerate(index.tolist()):
+        L.orc_b1((seed) & M64, (offset + 2 * (k // 2)) & M64, 2, mu, sigma, _p(pair))
+        out[t] = pair[k % 2]
+    return out
+
+
+def b1_parallel(seed: int, offset: int, n: int, mu: float = 0.0, sigma: float = 1.0,
+                threads: int | None = None, chunk_pairs: int = 1 << 20) -> np.ndarray:
+    """Algorithm B1 over a long stream, split into independent chunks of whole
+    pairs, each computed by one call of the reference."""
+    out = np.empty(n, dtype=np.float64)
+    npairs = (n + 1) // 2
+    L = lib()
+
+    def work(c0):
+        c1 = min(npairs, c0 + chunk_pairs)
+        m = min(n, 2 * c1) - 2 * c0
+        buf = out[2 * c0: 2 * c0 + m]
+        L.orc_b1(seed & M64, (offset + 2 * c0) & M64, m, mu, sigma, _p(buf))
+
+    with ThreadPoolExecutor(max_workers=threads or os.cpu_count()) as ex:
+        list(ex.map(work, range(0, npairs, chunk_pairs)))
+    return out
+
+
+# ---------------------------------------------------------------- Polar
+def polar(seed: int, offset: int, n: int, mu: float = 0.0, sigma: float = 1.0):
+    """n normals by Algorithm P; returns (values, uniforms consumed)."""
+    out = np.empty(max(n, 1), dtype=np.float64)
+    used = lib().orc_polar(seed & M64, offset & M64, n, mu, sigma, _p(out))
+    return out[:n], int(used)
+
+
+def polar_xy(xy, mu: float = 0.0, sigma: float = 1.0):
+    """Algorithm P on explicit integer candidates xy[j] = (X_j, Y_j).
+    Returns (compacted values, mask words, number accepted)."""
+    xy = np.ascontiguousarray(xy, dtype=np.int32).reshape(-1)
+    ncand = xy.size // 2
+    out = np.empty(max(2 * ncand, 1), dtype=np.float64)
+    masks = np.empty(max((ncand + 63) // 64, 1), dtype=np.uint64)
+    a = int(lib().orc_polar_xy(_p(xy), ncand, mu, sigma, _p(out), _p(masks)))
+    return out[:2 * a], masks[:(ncand + 63) // 64], a
+
+
+def polar_accept(X: int, Y: int) -> bool:
+    return bool(lib().orc_polar_accept(int(X), int(Y)))
+
+
+def polar_count(seed: int, offset: int, ncand: int) -> int:
+    return int(lib().orc_polar_count(seed & M64, offset & M64, ncand))
+
+
+def polar_trace(seed: int, offset: int, ncand: int):
+    nw = (ncand + 63) // 64
+    masks = np.empty(max(nw, 1), dtype=np.uint64)
+    pref = np.empty(max(nw, 1), dtype=np.uint64)
+    a = int(lib().orc_polar_trace(seed & M64, offset & M64, ncand, _p(masks), _p(pref)))
+    return masks[:nw], pref[:nw], a
+
+
+def polar_window(seed: int, offset: int, j0: int, ncand: int, mu: float = 0.0, sigma: float = 1.0):
+    out = np.empty(max(2 * ncand, 1), dtype=np.float64)
+    a = int(lib().orc_polar_window(seed & M64, offset & M64, j0, ncand, mu, sigma, _p(out)))
+    return out[:2 * a]
+
+
+def polar_chunk_counts(seed: int, offset: int, ncand: int, chunk: int, threads: int | None = None) -> np.ndarray:
+    """Accepted counts of consecutive candidate chunks [c, c + chunk) of the
+    stream, each from one call of the reference count."""
+    starts = list(range(0, ncand, chunk))
+    L = lib()
+
+    def work(c0):
+        return int(L.orc_polar_count(seed & M64, (offset + 2 * c0) & M64, min(chunk, ncand - c0)))
+
+    with ThreadPoolExecutor(max_workers=threads or os.cpu_count()) as ex:
+        return np.array(list(ex.map(work, starts)), dtype=np.int64)
+
+
+def polar_parallel(seed: int, offset: int, n: int, mu: float = 0.0, sigma: float = 1.0,
+                   threads: int | None = None, chunk: int = 1 << 20):
+    """Algorithm P over a long stream on several host threads: a count pass
+    over candidate chunks, an exclusive prefix of the counts, then each chunk
+    writes its accepted values at its prefix.  Same result as polar()."""
+    npairs = (n + 1) // 2
+    if n == 0:
+        return np.empty(0), 0
+    # Enough candidates: grow until the accepted count reaches npairs.
+    ncand = int(npairs * 4 / np.pi * 1.01) + 4096
+    while True:
+        counts = polar_chunk_counts(seed, offset, ncand, chunk, threads)
+        if counts.sum() >= npairs:
+            break
+        ncand *= 2
+    pref = np.concatenate([[0], np.cumsum(counts)])
+    last = int(np.searchsorted(pref, npairs, side="left")) - 1  # chunk holding pair npairs-1
+    out = np.empty(2 * int(pref[last + 1]), dtype=np.float64)
+    L = lib()
+
+    def work(ci):
+        c0 = ci * chunk
+        m = min(chunk, ncand - c0)
+        buf = out[2 * int(pref[ci]): 2 * int(pref[ci + 1])]
+        L.orc_polar_window(seed & M64, offset & M64, c0, m, mu, sigma, _p(buf))
+
+    with ThreadPoolExecutor(max_workers=threads or os.cpu_count()) as ex:
+        list(ex.map(work, range(last + 1)))
+    # candidate index of the npairs-th accepted pair -> consumed uniforms
+    c0 = last * chunk
+    masks, _, _ = polar_trace(seed, (offset + 2 * c0) & M64, min(chunk, ncand - c0))
+    need = npairs - int(pref[last])
+    bits = np.unpackbits(masks.view(np.uint8), bitorder="little")
+    jlast = c0 + int(np.flatnonzero(bits)[need - 1])
+    return out[:n], 2 * (jlast + 1)
+
+
+# ---------------------------------------------------------------- statistics
+def moments(x) -> np.ndarray:
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    out = np.empty(4, dtype=np.float64)
+    lib().orc_moments(_p(x), x.size, _p(out))
+    return out
+
+
+def normal_cdf(z: float) -> float:
+    return float(lib().orc_normal_cdf(z))
+
+
+def ks_normal(x, mu: float = 0.0, sigma: float = 1.0) -> float:
+    x = np.array(x, dtype=np.float64, copy=True)
+    return float(lib().orc_ks(_p(x), x.size, 0, mu, sigma))
+
+
+def ks_uniform(x) -> float:
+    x = np.array(x, dtype=np.float64, copy=True)
+    return float(lib().orc_ks(_p(x), x.size, 1, 0.0, 1.0))
+
+
+class use_library:
+    """Context manager that points this wrapper at another build of the
+    reference (the mutation tests compile deliberately broken copies of the
+    C source on the CPU and check that the pins reject them)."""
+
+    def __init__(self, path: str):
+        self.path = path
+        self.saved = None
+
+    def __enter__(self):
+        global _lib
+        lib()
+        self.saved = _lib
+        L = ctypes.CDLL(self.path)
+        for name in dir(self.saved):
+            if name.startswith("orc_"):
+                fn, ref = getattr(L, name), getattr(self.saved, name)
+                fn.restype, fn.argtypes = ref.restype, ref.argtypes
+        with _lock:
+            _lib = L
+        return L
+
+    def __exit__(self, *exc):
+        global _lib
+        with _lock:
+            _lib = self.saved
+        return False
+
+
+def build_variant(src_text: str, out_path: str) -> str:
+    """Compile a (modified) copy of the reference source to out_path."""
+    src_path = out_path + ".c"
+    with open(src_path, "w") as f:
+        f.write(src_text)
+    subprocess.run(["gcc", "-O2", "-std=c99", "-D_DEFAULT_SOURCE", "-ffp-contract=off", "-fPIC", "-shared",
+                    "-I", _HERE, "-o", out_path, src_path, "-lm"], check=True,
+                   stdout=subprocess.DEVNULL, stderr=subprocess.DEVNULL)
+    return out_path
+
+
+def source_text() -> str:
+    with open(_SRC) as f:
+        return f.read()

@@ -1,0 +1,335 @@
+/*
+ * nrng_oracle.c -- plain, slow, single-threaded FP64 reference for the
+ * normal-deviate path (Box-Muller Algorithm B1 and the Polar method,
+ * Algorithm P, of Brent, "Fast Normal Random Number Generators for Vector
+ * Processors", 1993).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library may include,
+ * link or call this file.  It is used by the test suite, by the smoke check
+ * and by the CPU-baseline leg of the benchmark, and by nothing else.  It
+ * shares no code, header, table or constant with the HIP kernels: the
+ * uniform generator below is written out again from its published
+ * definition.
+ *
+ * Build: gcc -O2 -std=c99 -ffp-contract=off -fPIC -shared (no fused
+ * multiply-add, so every line below is one IEEE-754 double operation).
+ *
+ * Pins (see the tests): the SplitMix64 check sequence, closed-form B1 and
+ * Polar values for chosen inputs, brute-force lattice counts of the Polar
+ * acceptance predicate on small grids, the pi/4 acceptance rate, the
+ * uniformity of the accepted s, sample moments and a Kolmogorov-Smirnov
+ * statistic against the normal CDF.
+ */
+#include <math.h>
+#include <stddef.h>
+#include <stdint.h>
+#include <stdlib.h>
+
+#include "nrng_oracle.h"
+
+/* ------------------------------------------------------------------------
+ * Uniform source.  The paper (Section 2) only assumes a generator of
+ * uniforms on [0,1) that may return 0 but never 1.  Here the uniforms are a
+ * counter-based stream: one SplitMix64 step (Steele, Lea and Flood, OOPSLA
+ * 2014) applied to the 64-bit counter  seed + offset + i  (mod 2^64).  A
+ * SplitMix64 step adds the golden-ratio increment and then applies the
+ * variant-13 mixing function (two xor-shift-multiply rounds and a final
+ * xor-shift).
+ * --------------------------------------------------------------------- */
+uint64_t orc_splitmix64(uint64_t x)
+{
+    uint64_t z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+/* i-th uniform of the stream: the top 53 bits of the hash, scaled by 2^-53,
+ * so u lies in [0, 1 - 2^-53] and may be exactly 0 but never 1 (the
+ * paper's assumption in Section 2, note a). */
+double orc_uniform(uint64_t seed, uint64_t ctr)
+{
+    return (double)(orc_splitmix64(seed + ctr) >> 11) * 0x1p-53;
+}
+
+/* i-th signed 32-bit integer of the stream: the top 32 bits of the hash,
+ * read as two's complement.  x = K * 2^-31 is then uniform on [-1, 1), the
+ * interval of step 1 of Algorithm P. */
+int32_t orc_int32(uint64_t seed, uint64_t ctr)
+{
+    return (int32_t)(uint32_t)(orc_splitmix64(seed + ctr) >> 32);
+}
+
+void orc_hash_block(uint64_t seed, uint64_t offset, uint64_t count, uint64_t *out)
+{
+    for (uint64_t i = 0; i < count; ++i)
+        out[i] = orc_splitmix64(seed + offset + i);
+}
+
+void orc_uniform_block(uint64_t seed, uint64_t offset, uint64_t count, double *out)
+{
+    for (uint64_t i = 0; i < count; ++i)
+        out[i] = orc_uniform(seed, offset + i);
+}
+
+void orc_int32_block(uint64_t seed, uint64_t offset, uint64_t count, int32_t *out)
+{
+    for (uint64_t i = 0; i < count; ++i)
+        out[i] = orc_int32(seed, offset + i);
+}
+
+/* ------------------------------------------------------------------------
+ * Algorithm B1 (Box-Muller), Section 2:
+ *   r = sigma * sqrt(-2 ln(1 - u));  x = r sin(2 pi v) + mu;  y = r cos(2 pi v) + mu.
+ * (1 - u) rather than u because u may be 0 (note a).  The angle is taken
+ * literally as 2 pi v with v in [0, 1); note b allows any interval of
+ * length 2 pi.  x (the sine) comes first in the output, then y.
+ * --------------------------------------------------------------------- */
+static void b1_pair(double u, double v, double mu, double sigma, double *x, double *y)
+{
+    double r = sigma * sqrt(-2.0 * log(1.0 - u));
+    double t = (2.0 * M_PI) * v;
+    *x = r * sin(t) + mu;
+    *y = r * cos(t) + mu;
+}
+
+/* B1 from explicit uniforms: pair p uses (u[p], v[p]) and writes out[2p],
+ * out[2p+1]. */
+void orc_b1_uv(const double *u, const double *v, uint64_t npairs, double mu, double sigma,
+               double *out)
+{
+    for (uint64_t p = 0; p < npairs; ++p)
+        b1_pair(u[p], v[p], mu, sigma, &out[2 * p], &out[2 * p + 1]);
+}
+
+/* B1 from explicit 64-bit hash words: pair p uses u = (w[2p] >> 11) 2^-53
+ * and v = (w[2p+1] >> 11) 2^-53. */
+void orc_b1_words(const uint64_t *w, uint64_t npairs, double mu, double sigma, double *out)
+{
+    for (uint64_t p = 0; p < npairs; ++p) {
+        double u = (double)(w[2 * p] >> 11) * 0x1p-53;
+        double v = (double)(w[2 * p + 1] >> 11) * 0x1p-53;
+        b1_pair(u, v, mu, sigma, &out[2 * p], &out[2 * p + 1]);
+    }
+}
+
+/* B1 over the counter stream: n normals from uniforms offset, offset+1, ...;
+ * pair k uses (u_{2k}, u_{2k+1}).  If n is odd the last pair writes only its
+ * first value.  Returns the number of uniforms consumed (2 * ceil(n/2)). */
+uint64_t orc_b1(uint64_t seed, uint64_t offset, uint64_t n, double mu, double sigma, double *out)
+{
+    uint64_t npairs = (n + 1) / 2;
+    for (uint64_t k = 0; k < npairs; ++k) {
+        double u = orc_uniform(seed, offset + 2 * k);
+        double v = orc_uniform(seed, offset + 2 * k + 1);
+        double x, y;
+        b1_pair(u, v, mu, sigma, &x, &y);
+        out[2 * k] = x;
+        if (2 * k + 1 < n)
+            out[2 * k + 1] = y;
+    }
+    return 2 * npairs;
+}
+
+/* ------------------------------------------------------------------------
+ * Algorithm P (the Polar method), Section 2:
+ *   1. x, y uniform on [-1, 1);  2. s = x^2 + y^2;  3. reject if s >= 1;
+ *   4. r = sigma * sqrt(-2 ln(s) / s), return r x + mu and r y + mu.
+ * Here x = X 2^-31 and y = Y 2^-31 for 32-bit signed X, Y, so
+ * s = S 2^-62 with the integer S = X^2 + Y^2 (at most 2^63, so it is held in
+ * an unsigned 64-bit word).  The test s >= 1 is S >= 2^62, decided exactly
+ * in integers.  S = 0 (s = 0) is rejected as well: step 4 would divide by
+ * zero, and the paper's suggested substitution of ln(1-s)/(1-s) does not
+ * give the same distribution, so the point is simply skipped.  s is S
+ * rounded to the nearest double, times 2^-62.
+ * --------------------------------------------------------------------- */
+int orc_polar_accept(int32_t X, int32_t Y)
+{
+    uint64_t S = (uint64_t)((int64_t)X * (int64_t)X) + (uint64_t)((int64_t)Y * (int64_t)Y);
+    return S != 0 && S < (1ull << 62);
+}
+
+static void polar_value(int32_t X, int32_t Y, double mu, double sigma, double *zx, double *zy)
+{
+    uint64_t S = (uint64_t)((int64_t)X * (int64_t)X) + (uint64_t)((int64_t)Y * (int64_t)Y);
+    double s = (double)S * 0x1p-62;
+    double r = sigma * sqrt(-2.0 * log(s) / s);
+    *zx = r * ((double)X * 0x1p-31) + mu;
+    *zy = r * ((double)Y * 0x1p-31) + mu;
+}
+
+/* Polar from explicit integer pairs: candidate j is (xy[2j], xy[2j+1]).
+ * Accepted candidates are written in increasing j (stable order) as
+ * out[2a], out[2a+1] where a counts earlier accepted candidates.  If
+ * mask_words is non-null, bit j%64 of mask_words[j/64] is set iff candidate
+ * j is accepted.  Returns the number of accepted candidates. */
+uint64_t orc_polar_xy(const int32_t *xy, uint64_t ncand, double mu, double sigma, double *out,
+                      uint64_t *mask_words)
+{
+    uint64_t a = 0;
+    if (mask_words)
+        for (uint64_t w = 0; w < (ncand + 63) / 64; ++w)
+            mask_words[w] = 0;
+    for (uint64_t j = 0; j < ncand; ++j) {
+        int32_t X = xy[2 * j], Y = xy[2 * j + 1];
+        if (!orc_polar_accept(X, Y))
+            continue;
+        if (mask_words)
+            mask_words[j / 64] |= 1ull << (j % 64);
+        if (out)
+            polar_value(X, Y, mu, sigma, &out[2 * a], &out[2 * a + 1]);
+        ++a;
+    }
+    return a;
+}
+
+/* Polar over the counter stream: candidate j uses the 32-bit integers at
+ * counters offset + 2j and offset + 2j + 1.  Writes exactly n normals (the
+ * second value of the last accepted pair is dropped when n is odd) and
+ * returns the number of uniforms consumed, 2 (j_last + 1), where j_last is
+ * the candidate that supplied the last value (0 when n = 0). */
+uint64_t orc_polar(uint64_t seed, uint64_t offset, uint64_t n, double mu, double sigma,
+                   double *out)
+{
+    uint64_t written = 0, j = 0;
+    while (written < n) {
+        int32_t X = orc_int32(seed, offset + 2 * j);
+        int32_t Y = orc_int32(seed, offset + 2 * j + 1);
+        if (orc_polar_accept(X, Y)) {
+            double zx, zy;
+            polar_value(X, Y, mu, sigma, &zx, &zy);
+            out[written++] = zx;
+            if (written < n)
+                out[written++] = zy;
+        }
+        ++j;
+    }
+    return 2 * j;
+}
+
+/* Number of accepted candidates among candidates [0, ncand) of the stream
+ * starting at counter offset (the predicate only; no values). */
+uint64_t orc_polar_count(uint64_t seed, uint64_t offset, uint64_t ncand)
+{
+    uint64_t a = 0;
+    for (uint64_t j = 0; j < ncand; ++j)
+        a += (uint64_t)orc_polar_accept(orc_int32(seed, offset + 2 * j),
+                                        orc_int32(seed, offset + 2 * j + 1));
+    return a;
+}
+
+/* Accept masks and output indices for candidates [0, ncand): bit j%64 of
+ * mask_words[j/64] is the accept bit of candidate j, and word_prefix[w] is
+ * the number of accepted candidates before candidate 64 w (so accepted
+ * candidate j lands at output pair word_prefix[j/64] + popcount of the lower
+ * bits of its word).  Returns the total accepted. */
+uint64_t orc_polar_trace(uint64_t seed, uint64_t offset, uint64_t ncand, uint64_t *mask_words,
+                         uint64_t *word_prefix)
+{
+    uint64_t a = 0;
+    for (uint64_t w = 0; w < (ncand + 63) / 64; ++w) {
+        uint64_t m = 0;
+        if (word_prefix)
+            word_prefix[w] = a;
+        for (uint64_t b = 0; b < 64 && 64 * w + b < ncand; ++b) {
+            uint64_t j = 64 * w + b;
+            if (orc_polar_accept(orc_int32(seed, offset + 2 * j),
+                                 orc_int32(seed, offset + 2 * j + 1))) {
+                m |= 1ull << b;
+                ++a;
+            }
+        }
+        mask_words[w] = m;
+    }
+    return a;
+}
+
+/* Values of the accepted candidates in the window [j0, j0 + ncand) of the
+ * stream (candidate indices relative to offset), written compactly in stream
+ * order; returns how many pairs were written.  Together with
+ * orc_polar_count(seed, offset, j0), which gives the output pair index of
+ * the first of them, this lets a test check any slice of a long stream. */
+uint64_t orc_polar_window(uint64_t seed, uint64_t offset, uint64_t j0, uint64_t ncand, double mu,
+                          double sigma, double *out)
+{
+    uint64_t a = 0;
+    for (uint64_t j = j0; j < j0 + ncand; ++j) {
+        int32_t X = orc_int32(seed, offset + 2 * j);
+        int32_t Y = orc_int32(seed, offset + 2 * j + 1);
+        if (orc_polar_accept(X, Y)) {
+            polar_value(X, Y, mu, sigma, &out[2 * a], &out[2 * a + 1]);
+            ++a;
+        }
+    }
+    return a;
+}
+
+/* ------------------------------------------------------------------------
+ * Statistics for the distribution checks (Section 2: the outputs are
+ * independent N(mu, sigma^2); in Algorithm P, s is uniform on [0, 1)).
+ * --------------------------------------------------------------------- */
+
+/* Pairwise (cascade) summation of f(x_i) for the central moments. */
+static double pw_sum_pow(const double *x, uint64_t n, double c, int p)
+{
+    if (n <= 64) {
+        double s = 0.0;
+        for (uint64_t i = 0; i < n; ++i) {
+            double d = x[i] - c, t = d;
+            for (int k = 1; k < p; ++k)
+                t = t * d;
+            s += (p == 0) ? 1.0 : t;
+        }
+        return s;
+    }
+    uint64_t h = n / 2;
+    return pw_sum_pow(x, h, c, p) + pw_sum_pow(x + h, n - h, c, p);
+}
+
+/* out[0] = mean, out[1] = variance (1/n), out[2] = skewness, out[3] =
+ * kurtosis (not excess: 3 for a normal sample). */
+void orc_moments(const double *x, uint64_t n, double *out)
+{
+    double mean = pw_sum_pow(x, n, 0.0, 1) / (double)n;
+    double m2 = pw_sum_pow(x, n, mean, 2) / (double)n;
+    double m3 = pw_sum_pow(x, n, mean, 3) / (double)n;
+    double m4 = pw_sum_pow(x, n, mean, 4) / (double)n;
+    out[0] = mean;
+    out[1] = m2;
+    out[2] = m3 / (m2 * sqrt(m2));
+    out[3] = m4 / (m2 * m2);
+}
+
+double orc_normal_cdf(double z)
+{
+    return 0.5 * erfc(-z / M_SQRT2);
+}
+
+static int cmp_double(const void *a, const void *b)
+{
+    double x = *(const double *)a, y = *(const double *)b;
+    return (x > y) - (x < y);
+}
+
+/* Kolmogorov-Smirnov statistic D = sup |F_n - F| of the sample x (sorted in
+ * place) against F = Phi((z - mu) / sigma) when kind = 0, or against the
+ * uniform CDF on [0, 1) when kind = 1. */
+double orc_ks(double *x, uint64_t n, int kind, double mu, double sigma)
+{
+    qsort(x, (size_t)n, sizeof(double), cmp_double);
+    double d = 0.0;
+    for (uint64_t i = 0; i < n; ++i) {
+        double f;
+        if (kind == 0)
+            f = orc_normal_cdf((x[i] - mu) / sigma);
+        else
+            f = x[i] < 0.0 ? 0.0 : (x[i] > 1.0 ? 1.0 : x[i]);
+        double lo = f - (double)i / (double)n;
+        double hi = (double)(i + 1) / (double)n - f;
+        if (lo > d)
+            d = lo;
+        if (hi > d)
+            d = hi;
+    }
+    return d;
+}

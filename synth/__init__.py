@@ -1,0 +1,109 @@
+"""Seeded synthetic inputs shared by the tests, the smoke check and the
+benchmark.
+
+This module holds none of the method's arithmetic: it only draws workload
+parameters and explicit test inputs from NumPy's PCG64 generator with fixed
+seeds.  The normal deviates themselves are always driven by the SplitMix64
+counter stream, which the oracle and the HIP library each implement on their
+own from its published definition.
+
+Workload recipes (the paper has no dataset; its workload is "many deviates,
+long vectors"):
+
+* single stream: ``n`` normals from counter ``offset`` of stream ``seed``;
+* batched: ``nstreams`` streams whose lengths are log-uniform on
+  [1e2, 1e6], means uniform on (-10, 10), standard deviations uniform on
+  (0.1, 5), each with its own 64-bit seed, packed back to back in one output
+  buffer;
+* explicit hash words / integer pairs for the test hooks, including the
+  edge cases of each transform.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+BATCH_SEED = 0xBA7C4
+
+
+def rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def batched_streams(nstreams: int = 4096, seed: int = BATCH_SEED, n_lo: float = 1e2, n_hi: float = 1e6,
+                    mu_lim: float = 10.0, sigma_lo: float = 0.1, sigma_hi: float = 5.0) -> dict:
+    """Per-stream parameters of the batched workload.
+
+    Lengths are floor(10^U) with U uniform on [log10 n_lo, log10 n_hi], capped
+    at n_hi; offsets are 0; the output layout is packed (out_off is the
+    exclusive prefix sum of the lengths)."""
+    g = rng(seed)
+    lo, hi = np.log10(n_lo), np.log10(n_hi)
+    n = np.minimum(np.floor(10.0 ** g.uniform(lo, hi, nstreams)), n_hi).astype(np.uint64)
+    mu = g.uniform(-mu_lim, mu_lim, nstreams)
+    sigma = g.uniform(sigma_lo, sigma_hi, nstreams)
+    seeds = g.integers(0, 2**64, nstreams, dtype=np.uint64, endpoint=False)
+    offset = np.zeros(nstreams, dtype=np.uint64)
+    out_off = np.zeros(nstreams, dtype=np.uint64)
+    if nstreams > 1:
+        out_off[1:] = np.cumsum(n[:-1], dtype=np.uint64)
+    return {"n": n, "mu": mu, "sigma": sigma, "seed": seeds, "offset": offset, "out_off": out_off,
+            "total": int(n.sum())}
+
+
+def random_words(count: int, seed: int = 11) -> np.ndarray:
+    return rng(seed).integers(0, 2**64, count, dtype=np.uint64, endpoint=False)
+
+
+def b1_edge_words(seed: int = 12) -> np.ndarray:
+    """Explicit 64-bit hash words for the B1 test hook, as (u-word, v-word)
+    pairs: exact hand-value inputs, the smallest and largest u, u just
+    around 1/2, angles at every eighth of a turn and just beside them, and
+    random pairs with u very close to 0 or 1."""
+    g = rng(seed)
+    T = 1 << 11          # one unit in the last place of a 53-bit uniform
+    H = 1 << 63          # u = 1/2
+    top = (1 << 64) - T  # u = 1 - 2^-53
+    us = [0, T, 2 * T, 3 * T, H - T, H, H + T, 3 << 62, top, top - T, top - 2 * T]
+    vs = [(k << 61) + d for k in range(8) for d in (0, T, (1 << 64) - T)]
+    vs = [v % (1 << 64) for v in vs]
+    pairs = [(u, v) for u in us for v in vs]
+    small = g.integers(0, 1 << 40, 256, dtype=np.uint64)
+    big = (np.uint64((1 << 64) - 1) - g.integers(0, 1 << 40, 256, dtype=np.uint64))
+    rv = g.integers(0, 2**64, 512, dtype=np.uint64, endpoint=False)
+    w = np.array(pairs, dtype=np.uint64).reshape(-1)
+    w2 = np.stack([np.concatenate([small, big]), rv], axis=1).reshape(-1)
+    return np.concatenate([w, w2]).astype(np.uint64)
+
+
+def polar_edge_xy(seed: int = 13) -> np.ndarray:
+    """Explicit int32 candidate pairs (X, Y) for the Polar test hook: the
+    hand-value points, the four points on the circle S = 2^62, the origin,
+    points one unit inside and outside the circle along both axes and the
+    diagonal, small-s points, and dense windows around the circle."""
+    g = rng(seed)
+    R = 1 << 31
+    pts = [(1 << 30, 0), (1 << 30, 1 << 30), (1, 0), (0, 1), (-R, 0), (0, -R), (0, 0),
+           (R - 1, 0), (0, R - 1), (-(R - 1), 0), (-R, -R), (-R, R - 1), (R - 1, R - 1),
+           (-1, -1), (1, -1), (3, 4), (-R, 1), (1, -R)]
+    # points near the circle along the diagonal: X = Y = floor(2^31 / sqrt 2) + d
+    c = int(np.floor(R / np.sqrt(2.0)))
+    pts += [(c + d, c + e) for d in range(-2, 3) for e in range(-2, 3)]
+    pts += [(-(c + d), c + e) for d in range(-2, 3) for e in range(-2, 3)]
+    # tiny s (s < 2^-20 <=> S < 2^42 <=> |X|,|Y| below about 2^21)
+    small = g.integers(-(1 << 21), 1 << 21, (512, 2))
+    # random points on a thin annulus around the circle
+    th = g.uniform(0, 2 * np.pi, 4096)
+    rad = R * (1.0 + g.uniform(-1e-6, 1e-6, 4096))
+    ring = np.stack([np.round(rad * np.cos(th)), np.round(rad * np.sin(th))], axis=1)
+    ring = np.clip(ring, -R, R - 1).astype(np.int64)
+    uni = g.integers(-R, R, (8192, 2))
+    allp = np.concatenate([np.array(pts, dtype=np.int64), small, ring, uni]).astype(np.int64)
+    return allp.astype(np.int32).reshape(-1)
+
+
+def slice_starts(count: int, length: int, span: int, seed: int = 0x51CE) -> np.ndarray:
+    """Sorted, even start indices of sampled slices [s, s + length) inside
+    [0, span)."""
+    g = rng(seed)
+    s = g.integers(0, span - length, count)
+    return np.sort(s - (s % 2)).astype(np.int64)

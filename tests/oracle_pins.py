@@ -1,0 +1,294 @@
+"""Pins of the FP64 oracle to facts outside itself.
+
+Each check raises AssertionError on failure.  They are run directly by
+test_oracle_pins.py and, against deliberately broken CPU builds of the
+oracle, by test_oracle_mutants.py (which requires every planted mistake to
+trip at least one of them).
+
+What pins what:
+  * the SplitMix64 check sequence (published test vector) pins the uniform
+    generator, and the definitions u = (k >> 11) 2^-53 and X = int32(k >> 32)
+    are checked against those published words;
+  * closed-form values of Algorithms B1 and P (Section 2) pin the
+    transforms, with inputs chosen so that swapping u and v, sin and cos, x
+    and y, dropping a factor of 2 or of s, or using u instead of 1 - u all
+    change the result;
+  * a brute-force lattice count (integer arithmetic written here) pins the
+    acceptance predicate, including the boundary circle S = 2^62;
+  * the acceptance rate pi/4, the uniformity of the accepted s and of the
+    polar angle, and moments / KS against the normal CDF pin the stream
+    composition statistically;
+  * SciPy pins the oracle's statistics routines.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+import oracle as O
+from helpers import closed_form, golden_rows, stat_bounds, ulp_dist64
+
+GAMMA = 0x9E3779B97F4A7C15
+M64 = (1 << 64) - 1
+
+
+def _published():
+    rows = []
+    import os
+    from helpers import GOLDEN
+    with open(os.path.join(GOLDEN, "splitmix64_check.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                i, v = line.split()
+                rows.append((int(i), int(v, 16)))
+    return rows
+
+
+# ------------------------------------------------------------------ uniforms
+def check_splitmix_published():
+    for i, v in _published():
+        got = O.splitmix64((i * GAMMA) & M64)
+        assert got == v, (i, hex(got), hex(v))
+
+
+def check_stream_definitions():
+    pub = dict(_published())
+    # u_i = (k >> 11) 2^-53 and X_i = int32(k >> 32) with k = splitmix64(seed + offset + i)
+    for i in range(4):
+        seed = (i * GAMMA) & M64
+        u = O.uniforms(seed, 0, 1)[0]
+        assert u == (pub[i] >> 11) * 2.0**-53, i
+        X = int(O.int32s(seed, 0, 1)[0])
+        hi = pub[i] >> 32
+        assert X == (hi - (1 << 32) if hi >= (1 << 31) else hi), i
+        assert int(O.hashes(seed, 0, 1)[0]) == pub[i]
+    # the counter is seed + offset + i, wrapping mod 2^64
+    assert int(O.hashes(M64, 0, 2)[1]) == pub[0]
+    assert int(O.hashes(M64 - 5, 3, 4)[3]) == pub[0]
+    a = O.hashes(12345, 678, 16)
+    b = O.hashes(12345 + 678, 0, 16)
+    c = O.hashes(0, 12345 + 678, 16)
+    assert np.array_equal(a, b) and np.array_equal(a, c)
+    assert np.all(O.uniforms(3, 0, 4096) < 1.0) and np.all(O.uniforms(3, 0, 4096) >= 0.0)
+
+
+# ------------------------------------------------------------------ B1
+def check_b1_hand():
+    rows = golden_rows("b1_hand_values.txt")
+    u = np.array([closed_form(r[0]) for r in rows])
+    v = np.array([closed_form(r[1]) for r in rows])
+    out = O.b1_uv(u, v).reshape(-1, 2)
+    for k, r in enumerate(rows):
+        for c in range(2):
+            want = closed_form(r[2 + c])
+            budget = int(r[4])
+            got = out[k, c]
+            if want == 0.0:
+                assert abs(got) <= 1e-15, (r, c, got)
+            else:
+                assert ulp_dist64([got], [want])[0] <= budget, (r, c, got, want)
+    # mu and sigma enter as sigma * (...) + mu
+    out2 = O.b1_uv(u, v, mu=-3.0, sigma=2.5).reshape(-1, 2)
+    assert np.allclose(out2, -3.0 + 2.5 * out, rtol=0, atol=1e-14)
+
+
+def check_b1_words_definition():
+    # u = (w >> 11) 2^-53 for the first word of a pair, v likewise for the second
+    w = np.array([1 << 63, 1 << 61, 3 << 62, 1 << 62, 0, (12345 << 11) + 7, ((1 << 53) - 1) << 11, 1 << 62],
+                 dtype=np.uint64)
+    got = O.b1_words(w)
+    want = O.b1_uv([0.5, 0.75, 0.0, 1 - 2.0**-53], [0.125, 0.25, 12345 * 2.0**-53, 0.25])
+    assert np.array_equal(got, want)
+
+
+def check_b1_composition():
+    seed, off, n = 0x5EED, 1000, 4097
+    z, used = O.b1(seed, off, n)
+    assert used == 2 * ((n + 1) // 2)
+    u = O.uniforms(seed, off, used)
+    ref = O.b1_uv(u[0::2], u[1::2])[:n]
+    assert np.array_equal(z, ref)
+    # raw words give the same stream
+    assert np.array_equal(O.b1_words(O.hashes(seed, off, used))[:n], ref)
+    # concatenation: the stream from offset off + 2k continues the same values
+    z2, _ = O.b1(seed, off + 2 * 100, n - 200)
+    assert np.array_equal(z2, z[200:])
+    # mu, sigma
+    zs, _ = O.b1(seed, off, n, mu=1.5, sigma=0.5)
+    assert np.allclose(zs, 1.5 + 0.5 * z, rtol=0, atol=1e-14)
+
+
+# ------------------------------------------------------------------ Polar
+def check_polar_hand():
+    rows = golden_rows("polar_hand_values.txt")
+    xy = np.array([[int(r[0]), int(r[1])] for r in rows], dtype=np.int64).astype(np.int32)
+    out, masks, a = O.polar_xy(xy)
+    acc = [int(r[2]) for r in rows]
+    assert a == sum(acc)
+    bits = [(int(masks[j // 64]) >> (j % 64)) & 1 for j in range(len(rows))]
+    assert bits == acc, (bits, acc)
+    vals = out.reshape(-1, 2)
+    k = 0
+    for r in rows:
+        if r[2] == "0":
+            assert not O.polar_accept(int(r[0]), int(r[1]))
+            continue
+        for c in range(2):
+            want = closed_form(r[3 + c])
+            got = vals[k, c]
+            if want == 0.0:
+                assert got == 0.0, (r, got)
+            else:
+                assert ulp_dist64([got], [want])[0] <= 4, (r, c, got, want)
+        k += 1
+    out2, _, _ = O.polar_xy(xy, mu=2.0, sigma=3.0)
+    assert np.allclose(out2, 2.0 + 3.0 * out, rtol=0, atol=1e-13)
+
+
+def lattice_count(b: int) -> int:
+    """#{(x, y) in [-2^(b-1), 2^(b-1))^2 : 0 < x^2 + y^2 < 2^(2b-2)}, by
+    counting, for each x, the integers y with y^2 < R^2 - x^2."""
+    R2 = 1 << (2 * b - 2)
+    h = 1 << (b - 1)
+    tot = 0
+    for x in range(-h, h):
+        rem = R2 - 1 - x * x
+        if rem < 0:
+            continue
+        m = math.isqrt(rem)                 # |y| <= m
+        lo, hi = max(-m, -h), min(m, h - 1)
+        tot += hi - lo + 1
+    return tot - 1                          # drop the origin
+
+
+def check_polar_lattice(bmax: int = 10):
+    for b in range(1, bmax + 1):
+        h = 1 << (b - 1)
+        g = np.arange(-h, h, dtype=np.int64)
+        X, Y = np.meshgrid(g, g, indexing="ij")
+        shift = 32 - b
+        xy = np.stack([X.ravel() << shift, Y.ravel() << shift], axis=1).astype(np.int32)
+        _, masks, a = O.polar_xy(xy)
+        assert a == lattice_count(b), (b, a, lattice_count(b))
+    # the four points on the circle S = 2^62 and their neighbours
+    R = 1 << 31
+    for (x, y, acc) in [(-R, 0, 0), (0, -R, 0), (-R, -R, 0), (R - 1, 0, 1), (0, R - 1, 1), (-R + 1, 0, 1),
+                        (-R, 1, 0), (0, 0, 0), (1, 0, 1), (0, 1, 1)]:
+        assert O.polar_accept(x, y) == bool(acc), (x, y)
+    # random points against exact Python integers
+    g = np.random.Generator(np.random.PCG64(99))
+    pts = g.integers(-R, R, (20000, 2))
+    _, masks, a = O.polar_xy(pts.astype(np.int32))
+    want = [(0 < int(x) * int(x) + int(y) * int(y) < (1 << 62)) for x, y in pts]
+    bits = np.unpackbits(masks.view(np.uint8), bitorder="little")[:len(want)].astype(bool)
+    assert np.array_equal(bits, np.array(want))
+
+
+def check_polar_composition():
+    seed, off, n = 7, 12, 20001
+    z, used = O.polar(seed, off, n)
+    ncand = used // 2
+    xy = O.int32s(seed, off, used)
+    ref, masks, a = O.polar_xy(xy)
+    assert a == (n + 1) // 2
+    # the last candidate consumed is the one that supplied the last value
+    assert (int(masks[(ncand - 1) // 64]) >> ((ncand - 1) % 64)) & 1 == 1
+    assert np.array_equal(z, ref[:n])
+    # trace and count agree with the mask of the explicit path
+    tm, tp, ta = O.polar_trace(seed, off, ncand)
+    assert np.array_equal(tm, masks) and ta == a
+    pc = np.concatenate([[0], np.cumsum([bin(int(m)).count("1") for m in masks])])[:-1]
+    assert np.array_equal(tp.astype(np.int64), pc)
+    assert O.polar_count(seed, off, ncand) == a
+    # a window of the stream reproduces the same slice
+    j0 = 1000
+    w = O.polar_window(seed, off, j0, 3000)
+    before = O.polar_count(seed, off, j0)
+    assert np.array_equal(w, ref[2 * before: 2 * before + w.size])
+    # concatenation: restarting at the consumed offset continues the stream
+    z1, used1 = O.polar(seed, off, 1000)
+    z2, used2 = O.polar(seed, off + used1, n - 1000)
+    assert np.array_equal(np.concatenate([z1, z2]), z) and used1 + used2 == used
+
+
+def check_polar_accept_rate(ncand: int = 1 << 21):
+    a = O.polar_count(0xACCE, 0, ncand)
+    p = math.pi / 4
+    assert abs(a / ncand - p) < 5 * math.sqrt(p * (1 - p) / ncand), a / ncand
+
+
+def check_polar_s_uniform(ncand: int = 1 << 19):
+    from scipy import stats
+    xy = O.int32s(0x5, 0, 2 * ncand).astype(np.int64).reshape(-1, 2)
+    S = xy[:, 0] ** 2 + xy[:, 1] ** 2          # exact in int64 except at S = 2^63
+    _, masks, a = O.polar_xy(xy.astype(np.int32))
+    bits = np.unpackbits(masks.view(np.uint8), bitorder="little")[:ncand].astype(bool)
+    s = S[bits].astype(np.float64) * 2.0**-62
+    assert s.size == a
+    assert stats.kstest(s, "uniform").statistic < 1.95 / math.sqrt(a)
+
+
+def _dist_checks(z: np.ndarray):
+    from scipy import stats
+    N = z.size
+    bd = stat_bounds(N)
+    assert abs(z.mean()) < bd["mean"], z.mean()
+    assert abs(z.var() - 1) < bd["var"], z.var()
+    assert abs(stats.skew(z)) < bd["skew"]
+    assert abs(stats.kurtosis(z, fisher=False) - 3) < bd["kurt"]
+    assert stats.kstest(z, "norm").statistic < bd["ks"]
+    r = np.corrcoef(z[:-1], z[1:])[0, 1]
+    assert abs(r) < 5 / math.sqrt(N)
+
+
+def check_b1_distribution(n: int = 1 << 20):
+    z, _ = O.b1(1, 0, n)
+    _dist_checks(z)
+    # the angle of each pair is uniform: (x, y) = r (sin t, cos t)
+    from scipy import stats
+    ang = np.arctan2(z[0::2], z[1::2]) / (2 * math.pi) % 1.0
+    assert stats.kstest(ang, "uniform").statistic < 1.95 / math.sqrt(ang.size)
+
+
+def check_polar_distribution(n: int = 1 << 20):
+    z, _ = O.polar(7, 0, n)
+    _dist_checks(z)
+    from scipy import stats
+    ang = (np.arctan2(z[1::2], z[0::2]) / (2 * math.pi)) % 1.0
+    assert stats.kstest(ang, "uniform").statistic < 1.95 / math.sqrt(ang.size)
+    # r^2 / 2 = -ln s is exponential(1) for the accepted s
+    e = 0.5 * (z[0::2] ** 2 + z[1::2] ** 2)
+    assert stats.kstest(e, "expon").statistic < 1.95 / math.sqrt(e.size)
+
+
+def check_stats_routines():
+    from scipy import special, stats
+    g = np.random.Generator(np.random.PCG64(5))
+    x = g.standard_normal(50001) * 1.7 + 0.3
+    m = O.moments(x)
+    assert abs(m[0] - x.mean()) < 1e-12
+    assert abs(m[1] - x.var()) < 1e-12
+    assert abs(m[2] - stats.skew(x)) < 1e-10
+    assert abs(m[3] - stats.kurtosis(x, fisher=False)) < 1e-10
+    for z in (-8.0, -3.0, -0.5, 0.0, 0.7, 2.0, 5.0):
+        assert abs(O.normal_cdf(z) - special.ndtr(z)) < 1e-15
+    d = O.ks_normal(x, 0.3, 1.7)
+    assert abs(d - stats.kstest(x, "norm", args=(0.3, 1.7)).statistic) < 1e-12
+    # samples whose empirical CDF lies above and below the model, so that the
+    # supremum is attained on each side of the step
+    for shift in (-0.2, 0.2):
+        xs = x + shift
+        d = O.ks_normal(xs, 0.3, 1.7)
+        assert abs(d - stats.kstest(xs, "norm", args=(0.3, 1.7)).statistic) < 1e-12
+    for a, b in ((1.0, 1.3), (1.3, 1.0)):
+        y = g.beta(a, b, 10001)
+        assert abs(O.ks_uniform(y) - stats.kstest(y, "uniform").statistic) < 1e-12
+
+
+ALL_CHECKS = [
+    check_splitmix_published, check_stream_definitions, check_b1_hand, check_b1_words_definition,
+    check_b1_composition, check_polar_hand, check_polar_lattice, check_polar_composition,
+    check_polar_accept_rate, check_polar_s_uniform, check_b1_distribution, check_polar_distribution,
+    check_stats_routines,
+]

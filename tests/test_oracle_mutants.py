@@ -1,0 +1,84 @@
+"""Mutation tests of the oracle's pins (CPU only).
+
+Each case plants one plausible mistake in a copy of the oracle's C source
+(a dropped term, a wrong sign, shift, index or constant, a transposed
+operand), builds it with gcc into a temporary directory, and requires that at
+least one pin in oracle_pins.py rejects it.  The real oracle is untouched.
+"""
+import os
+import subprocess
+import sys
+import tempfile
+
+import pytest
+
+import oracle as O
+import oracle_pins as P
+
+MUTANTS = {
+    "gamma": ("0x9E3779B97F4A7C15ull", "0x9E3779B97F4A7C17ull"),
+    "shift30": ("(z >> 30)", "(z >> 31)"),
+    "shift27": ("(z >> 27)", "(z >> 28)"),
+    "final_shift": ("return z ^ (z >> 31);", "return z ^ (z >> 32);"),
+    "mul2": ("0x94D049BB133111EBull", "0x94D049BB133111EAull"),
+    "u_bits": ("orc_splitmix64(seed + ctr) >> 11) * 0x1p-53", "orc_splitmix64(seed + ctr) >> 12) * 0x1p-52"),
+    "int_hi": ("(orc_splitmix64(seed + ctr) >> 32)", "(orc_splitmix64(seed + ctr) >> 31)"),
+    "counter_no_offset": ("out[i] = orc_splitmix64(seed + offset + i);", "out[i] = orc_splitmix64(seed + i);"),
+    "b1_u_not_1mu": ("log(1.0 - u)", "log(u + 0x1p-60)"),
+    "b1_drop_2": ("sqrt(-2.0 * log(1.0 - u))", "sqrt(-log(1.0 - u))"),
+    "b1_pi": ("(2.0 * M_PI) * v", "M_PI * v"),
+    "b1_swap_sincos": ("*x = r * sin(t) + mu;\n    *y = r * cos(t) + mu;", "*x = r * cos(t) + mu;\n    *y = r * sin(t) + mu;"),
+    "b1_mu_sign": ("*y = r * cos(t) + mu;", "*y = r * cos(t) - mu;"),
+    "b1_sigma_dropped": ("double r = sigma * sqrt(-2.0 * log(1.0 - u));", "double r = sqrt(-2.0 * log(1.0 - u));"),
+    "b1_pair_order": ("double u = orc_uniform(seed, offset + 2 * k);\n        double v = orc_uniform(seed, offset + 2 * k + 1);",
+                      "double v = orc_uniform(seed, offset + 2 * k);\n        double u = orc_uniform(seed, offset + 2 * k + 1);"),
+    "b1_words_shift": ("double v = (double)(w[2 * p + 1] >> 11) * 0x1p-53;", "double v = (double)(w[2 * p + 1] >> 12) * 0x1p-52;"),
+    "b1_odd_n": ("if (2 * k + 1 < n)\n            out[2 * k + 1] = y;", "out[2 * k + 1] = y;"),
+    "polar_boundary": ("S != 0 && S < (1ull << 62)", "S != 0 && S <= (1ull << 62)"),
+    "polar_zero": ("S != 0 && S < (1ull << 62)", "S < (1ull << 62)"),
+    "polar_drop_div": ("sqrt(-2.0 * log(s) / s)", "sqrt(-2.0 * log(s))"),
+    "polar_drop_2": ("sqrt(-2.0 * log(s) / s)", "sqrt(-log(s) / s)"),
+    "polar_scale": ("double s = (double)S * 0x1p-62;", "double s = (double)S * 0x1p-63;"),
+    "polar_swap_xy": ("*zx = r * ((double)X * 0x1p-31) + mu;\n    *zy = r * ((double)Y * 0x1p-31) + mu;",
+                      "*zx = r * ((double)Y * 0x1p-31) + mu;\n    *zy = r * ((double)X * 0x1p-31) + mu;"),
+    "polar_x_scale": ("*zx = r * ((double)X * 0x1p-31) + mu;", "*zx = r * ((double)X * 0x1p-32) + mu;"),
+    "polar_sigma": ("double r = sigma * sqrt(-2.0 * log(s) / s);", "double r = sqrt(-2.0 * log(s) / s);"),
+    "polar_pairing": ("int32_t X = orc_int32(seed, offset + 2 * j);\n        int32_t Y = orc_int32(seed, offset + 2 * j + 1);\n        if (orc_polar_accept(X, Y)) {\n            double zx, zy;",
+                      "int32_t X = orc_int32(seed, offset + 2 * j + 1);\n        int32_t Y = orc_int32(seed, offset + 2 * j);\n        if (orc_polar_accept(X, Y)) {\n            double zx, zy;"),
+    "polar_consumed": ("    return 2 * j;\n}", "    return 2 * j + 2;\n}"),
+    "polar_odd": ("if (written < n)\n                out[written++] = zy;", "out[written++] = zy;"),
+    "polar_trace_prefix": ("word_prefix[w] = a;", "word_prefix[w] = a + 1;"),
+    "polar_window_start": ("for (uint64_t j = j0; j < j0 + ncand; ++j) {", "for (uint64_t j = j0 + 1; j < j0 + ncand; ++j) {"),
+    "kurtosis": ("out[3] = m4 / (m2 * m2);", "out[3] = m4 / m2;"),
+    "skew": ("out[2] = m3 / (m2 * sqrt(m2));", "out[2] = m3 / m2;"),
+    "ks_step": ("double hi = (double)(i + 1) / (double)n - f;", "double hi = (double)i / (double)n - f;"),
+    "cdf_sign": ("return 0.5 * erfc(-z / M_SQRT2);", "return 0.5 * erfc(z / M_SQRT2);"),
+}
+
+
+@pytest.fixture(scope="module")
+def mutant_results():
+    """Build every mutant and run the pins on each in its own process, a few
+    at a time."""
+    from concurrent.futures import ThreadPoolExecutor
+    src = O.source_text()
+    runner = os.path.join(os.path.dirname(os.path.abspath(__file__)), "mutant_runner.py")
+    with tempfile.TemporaryDirectory(prefix="nrng_mut_") as d:
+        def one(name):
+            old, new = MUTANTS[name]
+            if src.count(old) < 1:
+                return name, None, "mutation site not found"
+            path = O.build_variant(src.replace(old, new, 1), os.path.join(d, "mut_%s.so" % name))
+            r = subprocess.run([sys.executable, runner, path], capture_output=True, text=True, timeout=600)
+            return name, r.returncode, (r.stdout + r.stderr)[-400:]
+
+        with ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
+            res = {name: (rc, out) for name, rc, out in ex.map(one, sorted(MUTANTS))}
+    return res
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_reject_mutant(name, mutant_results):
+    rc, out = mutant_results[name]
+    assert rc is not None, out
+    assert rc != 0, "no pin rejects mutant %s" % name
