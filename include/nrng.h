@@ -1,0 +1,228 @@
+/*
+ * nrng.h -- C ABI of libnrng.so: normal random deviates on AMD Instinct
+ * MI355X (gfx950).
+ *
+ * The library turns a counter-based stream of uniform deviates into
+ * N(mu, sigma^2) deviates by the two methods of Section 2 of R. P. Brent,
+ * "Fast Normal Random Number Generators for Vector Processors" (1993):
+ *
+ *   Algorithm B1 (Box-Muller):  r = sigma sqrt(-2 ln(1 - u)),
+ *                               x = r sin(2 pi v) + mu,  y = r cos(2 pi v) + mu;
+ *   Algorithm P (Polar method): x, y uniform on [-1, 1), s = x^2 + y^2,
+ *                               reject if s >= 1, else r = sigma sqrt(-2 ln(s)/s)
+ *                               and return r x + mu, r y + mu.
+ *
+ * Uniform stream (identical in every entry point): counter c_i = seed +
+ * offset + i (mod 2^64) and hash k_i = SplitMix64(c_i), one generator step
+ * (add 0x9E3779B97F4A7C15, then the variant-13 mixer).
+ *   - B1 pair k uses u = (k_{2k} >> 11) 2^-53 and v = (k_{2k+1} >> 11) 2^-53
+ *     (u may be 0 but never 1, the paper's assumption in Section 2, note a).
+ *     Output 2k is the sine value x, output 2k+1 the cosine value y.
+ *   - Polar candidate j uses X = (int32)(k_{2j} >> 32) and
+ *     Y = (int32)(k_{2j+1} >> 32), i.e. x = X 2^-31, y = Y 2^-31 in [-1, 1).
+ *     With S = X^2 + Y^2 computed exactly in 64-bit integers, the candidate
+ *     is accepted iff 0 < S < 2^62 (s < 1 decided exactly; s = 0 rejected to
+ *     avoid the division by zero of step 4).  Accepted candidates are emitted
+ *     in increasing j (stable order): the a-th accepted pair writes outputs
+ *     2a and 2a+1.
+ *   - If n is odd the last pair contributes only its first value.
+ *   - Offsets and "consumed" counts are in uniforms (counter values), for both
+ *     methods: B1 consumes 2 ceil(n/2); Polar consumes 2 (j_last + 1) where
+ *     j_last is the candidate that supplied the last value.  Calling again with
+ *     offset + consumed continues the same stream exactly.
+ *
+ * Precision: NRNG_F64 output is computed in FP64 throughout (the plain FP64
+ * kernels).  NRNG_F32, NRNG_BF16 and NRNG_F16 are computed in FP32 (the Polar
+ * kernel switches to FP64 for ln(s)/s when s < 2^-20) and rounded to nearest
+ * even once into the output format.
+ *
+ * Conventions for every entry point:
+ *   - Pointers named out and d_* are device pointers on the current HIP
+ *     device, allocated and owned by the caller; the library never frees or
+ *     retains them.  `out` may have any element alignment.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream);
+ *     all work is enqueued asynchronously on it.  No entry point synchronises
+ *     the device unless its comment says so.
+ *   - Return value: NRNG_OK (0) or a negative nrng_status.  Argument errors
+ *     are reported before anything is launched and nothing is written.
+ *     Nothing prints and nothing aborts.
+ *   - The library keeps a small per-device workspace (look-back status words,
+ *     tile tables).  Calls that use it (Polar, batched) must be ordered on one
+ *     stream per device; concurrent such calls on different streams of one
+ *     device race.  The workspace grows on demand, which allocates; during
+ *     stream capture growth is refused with NRNG_ECAPTURE, so call
+ *     nrng_reserve() before capturing.
+ */
+#ifndef NRNG_H
+#define NRNG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Output element types. */
+enum nrng_dtype { NRNG_F64 = 0, NRNG_F32 = 1, NRNG_BF16 = 2, NRNG_F16 = 3 };
+
+/* Methods for nrng_batched. */
+enum nrng_method { NRNG_METHOD_B1 = 0, NRNG_METHOD_POLAR = 1 };
+
+/* Status codes. */
+enum nrng_status {
+    NRNG_OK = 0,
+    NRNG_EINVAL = -1,   /* bad pointer, non-finite mu/sigma, sigma < 0, bad method */
+    NRNG_EDTYPE = -2,   /* unknown dtype */
+    NRNG_ERANGE = -3,   /* size too large (counter range or workspace limits) */
+    NRNG_EHIP = -4,     /* a HIP runtime call or kernel launch failed */
+    NRNG_ENODEV = -5,   /* no usable GPU */
+    NRNG_ECAPTURE = -6, /* the call would allocate while the stream is capturing */
+    NRNG_ENOMEM = -7    /* device allocation failed */
+};
+
+/* Static description of a status code (never NULL). */
+const char *nrng_strerror(int status);
+
+/* Library version, major * 10000 + minor * 100 + patch. */
+int nrng_version(void);
+
+/* Initialise the current device: query it and allocate the base workspace.
+ * Optional (every entry point initialises lazily); allocates, so not for use
+ * during stream capture.  NRNG_ENODEV if no HIP device is usable. */
+int nrng_init(void);
+
+/* Pre-size the current device's workspace so that later calls with at most
+ * max_n normals per single-stream Polar call, and batched calls with at most
+ * max_streams streams and max_n normals in total, do not allocate (needed
+ * before capturing such calls in a graph).  Allocates; not capturable. */
+int nrng_reserve(uint64_t max_n, uint32_t max_streams);
+
+/* ------------------------------------------------------------------------
+ * Algorithm B1 (Box-Muller), Section 2, over one stream.
+ *   seed, offset  the stream and the first counter used (uniform units)
+ *   n             normals to write (0 is a no-op returning NRNG_OK)
+ *   mu, sigma     mean and standard deviation (finite, sigma >= 0)
+ *   out           n elements of `dtype`
+ * Consumes exactly 2 ceil(n/2) uniforms.  Embarrassingly parallel: each pair
+ * is computed independently and stored with 16-byte vector stores.
+ * ---------------------------------------------------------------------- */
+int nrng_boxmuller(uint64_t seed, uint64_t offset, uint64_t n, double mu, double sigma, void *out,
+                   int dtype, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Algorithm P (Polar method), Section 2, over one stream.
+ *   Arguments as nrng_boxmuller.  The acceptance test of step 3 and the
+ *   compaction of accepted pairs (the paper's vector gather, Section 2, and
+ *   the compress of triples (x_j, y_j, s_j), Section 4) are done in one pass:
+ *   wavefront ballots give each accepted candidate its rank in its tile and
+ *   tiles find their output offset by decoupled look-back, so accept masks
+ *   and output indices are exact integers.
+ *   d_consumed  optional device pointer (may be NULL): receives the number
+ *               of uniforms consumed, 2 (j_last + 1).  Written
+ *               asynchronously; no synchronisation.
+ * ---------------------------------------------------------------------- */
+int nrng_polar(uint64_t seed, uint64_t offset, uint64_t n, double mu, double sigma, void *out,
+               int dtype, void *stream, uint64_t *d_consumed);
+
+/* Polar method with a device-resident counter offset, for repeated fills
+ * captured in a HIP graph: reads the offset from *d_cursor when the kernel
+ * runs and advances *d_cursor by the number of uniforms consumed, so that
+ * successive calls (or graph replays) continue one stream.  Launches exactly
+ * one kernel and allocates nothing once the workspace is reserved
+ * (nrng_reserve(n, 0)); NRNG_ECAPTURE otherwise while capturing. */
+int nrng_polar_dev(uint64_t seed, uint64_t *d_cursor, uint64_t n, double mu, double sigma, void *out,
+                   int dtype, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Many independent streams in one persistent launch (plus one small set-up
+ * kernel that builds the tile table on the device).
+ *   method       NRNG_METHOD_B1 or NRNG_METHOD_POLAR
+ *   nstreams     number of streams (0 is a no-op)
+ *   d_seed[j], d_offset[j], d_n[j]  stream j's seed, first counter, length
+ *   d_out_off[j] element offset of stream j's output in `out`; NULL means
+ *                packed (exclusive prefix sum of d_n)
+ *   d_mu[j], d_sigma[j]             per-stream mean and standard deviation
+ *   out, out_len output buffer and its length in elements; streams whose
+ *                range [out_off, out_off + n) does not fit are skipped
+ *   d_consumed   optional (may be NULL): d_consumed[j] receives stream j's
+ *                consumed uniforms, or UINT64_MAX if the stream was skipped.
+ * Stream j's values equal those of nrng_boxmuller / nrng_polar called alone
+ * with (d_seed[j], d_offset[j], d_n[j], d_mu[j], d_sigma[j]), bit for bit.
+ * The total of d_n over valid streams must not exceed out_len; otherwise the
+ * device-side check fails the whole call (every d_consumed[j] = UINT64_MAX,
+ * nothing written).  Per-stream mu and sigma are not validated on the host. */
+int nrng_batched(int method, uint32_t nstreams, const uint64_t *d_seed, const uint64_t *d_offset,
+                 const uint64_t *d_n, const uint64_t *d_out_off, const double *d_mu, const double *d_sigma,
+                 void *out, uint64_t out_len, int dtype, void *stream, uint64_t *d_consumed);
+
+/* ------------------------------------------------------------------------
+ * Repeated fills through a HIP graph: capture one nrng_polar_dev launch
+ * (with the workspace reserved beforehand) and return an instantiated graph
+ * in *graph.  Each nrng_fillgraph_launch replays it on `stream`, refilling
+ * `out` with the next n normals of the stream and advancing *d_cursor.
+ * The capture uses `stream`, which must not be capturing already. */
+int nrng_fillgraph_create(uint64_t seed, uint64_t *d_cursor, uint64_t n, double mu, double sigma, void *out,
+                          int dtype, void *stream, void **graph);
+int nrng_fillgraph_launch(void *graph, void *stream);
+int nrng_fillgraph_destroy(void *graph);
+
+/* ------------------------------------------------------------------------
+ * Launch configuration.  kernel: 0 = B1 single stream, 1 = Polar (single,
+ * device cursor and batched), 2 = B1 batched.  Sets the workgroup size and
+ * per-thread unroll used for `dtype`; NRNG_EINVAL if that pair is not one of
+ * the compiled variants (nrng_tune_variants lists them as (wg, unroll)
+ * pairs).  grid_per_cu (0 = from the occupancy query) caps the persistent
+ * grid at that many workgroups per compute unit. */
+int nrng_tune_set(int kernel, int dtype, uint32_t wg, uint32_t unroll, uint32_t grid_per_cu);
+int nrng_tune_get(int kernel, int dtype, uint32_t *wg, uint32_t *unroll, uint32_t *grid_per_cu);
+int nrng_tune_variants(int kernel, uint32_t *pairs, int max_pairs);
+
+/* ------------------------------------------------------------------------
+ * Test hooks: the production per-pair arithmetic and compaction fed from
+ * explicit inputs instead of the hash stream.
+ *
+ * nrng_test_b1_words: pair p uses u-word d_words[2p] and v-word
+ *   d_words[2p+1] (64-bit hash words); writes out[2p], out[2p+1].
+ * nrng_test_polar_xy: candidate j is (d_xy[2j], d_xy[2j+1]); accepted
+ *   candidates are written compactly in order to out (capacity 2 ncand);
+ *   d_mask_words (ceil(ncand/64) words, bit j%64 of word j/64 = accept) and
+ *   *d_count (number accepted) are written.
+ * nrng_polar_trace: the accept masks and, per 64-candidate word, the output
+ *   pair index of its first candidate (exclusive prefix), for candidates
+ *   [0, ncand) of stream (seed, offset), produced by the production Polar
+ *   kernel's predicate, ballots and look-back.
+ * nrng_test_polar_budget: nrng_polar with the look-back tile budget forced
+ *   to `tiles` (>= 1), to exercise the exact continuation path that runs
+ *   when a stream needs more candidates than its budget.
+ * ---------------------------------------------------------------------- */
+int nrng_test_b1_words(const uint64_t *d_words, uint64_t npairs, double mu, double sigma, void *out, int dtype,
+                       void *stream);
+int nrng_test_polar_xy(const int32_t *d_xy, uint64_t ncand, double mu, double sigma, void *out, int dtype,
+                       uint64_t *d_mask_words, uint64_t *d_count, void *stream);
+int nrng_polar_trace(uint64_t seed, uint64_t offset, uint64_t ncand, uint64_t *d_mask_words,
+                     uint64_t *d_word_prefix, void *stream);
+int nrng_test_polar_budget(uint64_t seed, uint64_t offset, uint64_t n, double mu, double sigma, void *out,
+                           int dtype, uint32_t tiles, void *stream, uint64_t *d_consumed);
+
+/* ------------------------------------------------------------------------
+ * Measurement probes (roofline ceilings and counter calibration).
+ * nrng_probe_store: write nbytes (multiple of 16) of a fixed pattern with
+ *   16-byte stores -- the store-only HBM ceiling.
+ * nrng_probe_copy: copy nbytes (multiple of 16) from src to dst -- a kernel
+ *   of known traffic for scaling hardware byte counters.
+ * nrng_probe_hash: nhash SplitMix64 hashes of counters seed + i, xor-reduced
+ *   into d_sink[0..gridsize) -- the hash-only VALU ceiling.
+ * ---------------------------------------------------------------------- */
+int nrng_probe_store(void *out, uint64_t nbytes, void *stream);
+int nrng_probe_copy(void *dst, const void *src, uint64_t nbytes, void *stream);
+int nrng_probe_hash(uint64_t seed, uint64_t nhash, uint64_t *d_sink, uint64_t sink_len, void *stream);
+
+/* Number of compute units of the current device (0 if none). */
+int nrng_device_cus(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NRNG_H */

@@ -1,0 +1,216 @@
+"""ctypes binding of libnrng.so (argument marshalling only).
+
+Every function has the name and argument order of the C entry point in
+include/nrng.h.  Buffer arguments accept a torch tensor on the GPU (its
+data_ptr() is passed), an integer device address, or None for NULL.  The
+stream argument accepts a torch.cuda.Stream, an integer hipStream_t, or None
+for torch's current stream on the current device.  A non-zero status raises
+NrngError.  There is no fallback: if the library is not built, the first
+call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libnrng.so")
+
+NRNG_F64, NRNG_F32, NRNG_BF16, NRNG_F16 = 0, 1, 2, 3
+NRNG_METHOD_B1, NRNG_METHOD_POLAR = 0, 1
+NRNG_OK, NRNG_EINVAL, NRNG_EDTYPE, NRNG_ERANGE = 0, -1, -2, -3
+NRNG_EHIP, NRNG_ENODEV, NRNG_ECAPTURE, NRNG_ENOMEM = -4, -5, -6, -7
+KERNEL_B1, KERNEL_POLAR, KERNEL_B1_BATCHED = 0, 1, 2
+
+_u64, _u32, _i32, _f64, _vp = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int, ctypes.c_double, ctypes.c_void_p
+
+_SIGS = {
+    "nrng_strerror": (ctypes.c_char_p, [_i32]),
+    "nrng_version": (_i32, []),
+    "nrng_init": (_i32, []),
+    "nrng_device_cus": (_i32, []),
+    "nrng_reserve": (_i32, [_u64, _u32]),
+    "nrng_boxmuller": (_i32, [_u64, _u64, _u64, _f64, _f64, _vp, _i32, _vp]),
+    "nrng_polar": (_i32, [_u64, _u64, _u64, _f64, _f64, _vp, _i32, _vp, _vp]),
+    "nrng_polar_dev": (_i32, [_u64, _vp, _u64, _f64, _f64, _vp, _i32, _vp]),
+    "nrng_batched": (_i32, [_i32, _u32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _u64, _i32, _vp, _vp]),
+    "nrng_fillgraph_create": (_i32, [_u64, _vp, _u64, _f64, _f64, _vp, _i32, _vp, ctypes.POINTER(_vp)]),
+    "nrng_fillgraph_launch": (_i32, [_vp, _vp]),
+    "nrng_fillgraph_destroy": (_i32, [_vp]),
+    "nrng_tune_set": (_i32, [_i32, _i32, _u32, _u32, _u32]),
+    "nrng_tune_get": (_i32, [_i32, _i32, ctypes.POINTER(_u32), ctypes.POINTER(_u32), ctypes.POINTER(_u32)]),
+    "nrng_tune_variants": (_i32, [_i32, ctypes.POINTER(_u32), _i32]),
+    "nrng_test_b1_words": (_i32, [_vp, _u64, _f64, _f64, _vp, _i32, _vp]),
+    "nrng_test_polar_xy": (_i32, [_vp, _u64, _f64, _f64, _vp, _i32, _vp, _vp, _vp]),
+    "nrng_polar_trace": (_i32, [_u64, _u64, _u64, _vp, _vp, _vp]),
+    "nrng_test_polar_budget": (_i32, [_u64, _u64, _u64, _f64, _f64, _vp, _i32, _u32, _vp, _vp]),
+    "nrng_probe_store": (_i32, [_vp, _u64, _vp]),
+    "nrng_probe_copy": (_i32, [_vp, _vp, _u64, _vp]),
+    "nrng_probe_hash": (_i32, [_u64, _u64, _vp, _u64, _vp]),
+}
+
+_lock = threading.Lock()
+_lib = None
+
+
+class NrngError(RuntimeError):
+    def __init__(self, fn: str, status: int, msg: str):
+        super().__init__("%s failed: %s (%d)" % (fn, msg, status))
+        self.status = status
+
+
+def lib() -> ctypes.CDLL:
+    """Load libnrng.so (raises if it has not been built)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError("libnrng.so is not built (%s); run __graft_entry__.build() or "
+                                   "python -m paper_1004_3105_amd.build" % LIB_PATH)
+            L = ctypes.CDLL(LIB_PATH)
+            for name, (res, args) in _SIGS.items():
+                f = getattr(L, name)
+                f.restype, f.argtypes = res, args
+            _lib = L
+    return _lib
+
+
+def _ptr(x):
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    if hasattr(x, "data_ptr"):
+        if not x.is_cuda:
+            raise ValueError("device tensor expected")
+        return x.data_ptr()
+    raise TypeError("expected a tensor, an int address or None, got %r" % type(x))
+
+
+def _stream(s):
+    if s is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(s, int):
+        return s
+    return s.cuda_stream
+
+
+def _check(fn: str, rc: int) -> int:
+    if rc != NRNG_OK:
+        raise NrngError(fn, rc, lib().nrng_strerror(rc).decode())
+    return rc
+
+
+def nrng_strerror(status: int) -> str:
+    return lib().nrng_strerror(status).decode()
+
+
+def nrng_version() -> int:
+    return lib().nrng_version()
+
+
+def nrng_init() -> None:
+    _check("nrng_init", lib().nrng_init())
+
+
+def nrng_device_cus() -> int:
+    return lib().nrng_device_cus()
+
+
+def nrng_reserve(max_n: int, max_streams: int = 0) -> None:
+    _check("nrng_reserve", lib().nrng_reserve(max_n, max_streams))
+
+
+def nrng_boxmuller(seed, offset, n, mu, sigma, out, dtype, stream=None) -> None:
+    _check("nrng_boxmuller", lib().nrng_boxmuller(seed & (2**64 - 1), offset & (2**64 - 1), n, mu, sigma,
+                                                  _ptr(out), dtype, _stream(stream)))
+
+
+def nrng_polar(seed, offset, n, mu, sigma, out, dtype, stream=None, d_consumed=None) -> None:
+    _check("nrng_polar", lib().nrng_polar(seed & (2**64 - 1), offset & (2**64 - 1), n, mu, sigma, _ptr(out),
+                                          dtype, _stream(stream), _ptr(d_consumed)))
+
+
+def nrng_polar_dev(seed, d_cursor, n, mu, sigma, out, dtype, stream=None) -> None:
+    _check("nrng_polar_dev", lib().nrng_polar_dev(seed & (2**64 - 1), _ptr(d_cursor), n, mu, sigma, _ptr(out),
+                                                  dtype, _stream(stream)))
+
+
+def nrng_batched(method, nstreams, d_seed, d_offset, d_n, d_out_off, d_mu, d_sigma, out, out_len, dtype,
+                 stream=None, d_consumed=None) -> None:
+    _check("nrng_batched", lib().nrng_batched(method, nstreams, _ptr(d_seed), _ptr(d_offset), _ptr(d_n),
+                                              _ptr(d_out_off), _ptr(d_mu), _ptr(d_sigma), _ptr(out), out_len,
+                                              dtype, _stream(stream), _ptr(d_consumed)))
+
+
+def nrng_fillgraph_create(seed, d_cursor, n, mu, sigma, out, dtype, stream) -> int:
+    h = _vp()
+    _check("nrng_fillgraph_create", lib().nrng_fillgraph_create(seed & (2**64 - 1), _ptr(d_cursor), n, mu, sigma,
+                                                                _ptr(out), dtype, _stream(stream),
+                                                                ctypes.byref(h)))
+    return h.value
+
+
+def nrng_fillgraph_launch(graph: int, stream=None) -> None:
+    _check("nrng_fillgraph_launch", lib().nrng_fillgraph_launch(graph, _stream(stream)))
+
+
+def nrng_fillgraph_destroy(graph: int) -> None:
+    _check("nrng_fillgraph_destroy", lib().nrng_fillgraph_destroy(graph))
+
+
+def nrng_tune_set(kernel, dtype, wg, unroll, grid_per_cu=0) -> None:
+    _check("nrng_tune_set", lib().nrng_tune_set(kernel, dtype, wg, unroll, grid_per_cu))
+
+
+def nrng_tune_get(kernel, dtype):
+    a, b, c = _u32(), _u32(), _u32()
+    _check("nrng_tune_get", lib().nrng_tune_get(kernel, dtype, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return a.value, b.value, c.value
+
+
+def nrng_tune_variants(kernel):
+    buf = (_u32 * 64)()
+    nv = lib().nrng_tune_variants(kernel, buf, 32)
+    if nv < 0:
+        _check("nrng_tune_variants", nv)
+    return [(buf[2 * i], buf[2 * i + 1]) for i in range(nv)]
+
+
+def nrng_test_b1_words(d_words, npairs, mu, sigma, out, dtype, stream=None) -> None:
+    _check("nrng_test_b1_words", lib().nrng_test_b1_words(_ptr(d_words), npairs, mu, sigma, _ptr(out), dtype,
+                                                          _stream(stream)))
+
+
+def nrng_test_polar_xy(d_xy, ncand, mu, sigma, out, dtype, d_mask_words, d_count, stream=None) -> None:
+    _check("nrng_test_polar_xy", lib().nrng_test_polar_xy(_ptr(d_xy), ncand, mu, sigma, _ptr(out), dtype,
+                                                          _ptr(d_mask_words), _ptr(d_count), _stream(stream)))
+
+
+def nrng_polar_trace(seed, offset, ncand, d_mask_words, d_word_prefix, stream=None) -> None:
+    _check("nrng_polar_trace", lib().nrng_polar_trace(seed & (2**64 - 1), offset & (2**64 - 1), ncand,
+                                                      _ptr(d_mask_words), _ptr(d_word_prefix), _stream(stream)))
+
+
+def nrng_test_polar_budget(seed, offset, n, mu, sigma, out, dtype, tiles, stream=None, d_consumed=None) -> None:
+    _check("nrng_test_polar_budget", lib().nrng_test_polar_budget(seed & (2**64 - 1), offset & (2**64 - 1), n, mu,
+                                                                  sigma, _ptr(out), dtype, tiles, _stream(stream),
+                                                                  _ptr(d_consumed)))
+
+
+def nrng_probe_store(out, nbytes, stream=None) -> None:
+    _check("nrng_probe_store", lib().nrng_probe_store(_ptr(out), nbytes, _stream(stream)))
+
+
+def nrng_probe_copy(dst, src, nbytes, stream=None) -> None:
+    _check("nrng_probe_copy", lib().nrng_probe_copy(_ptr(dst), _ptr(src), nbytes, _stream(stream)))
+
+
+def nrng_probe_hash(seed, nhash, d_sink, sink_len, stream=None) -> None:
+    _check("nrng_probe_hash", lib().nrng_probe_hash(seed & (2**64 - 1), nhash, _ptr(d_sink), sink_len,
+                                                    _stream(stream)))
+
+
+EXPORTED = sorted(_SIGS)

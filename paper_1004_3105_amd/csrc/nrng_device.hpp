@@ -1,0 +1,317 @@
+// nrng_device.hpp -- device-side building blocks of the normal-deviate
+// kernels for gfx950: the counter-based uniform source, the per-pair
+// transforms of Box-Muller (Algorithm B1) and the Polar method (Algorithm P)
+// [Brent 1993, Section 2], output conversion and store helpers, and the
+// wavefront primitives of the Polar compaction.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nrng {
+
+// ---------------------------------------------------------------------------
+// Uniform source.  Counter c = seed + offset + i (mod 2^64); hash
+// k = SplitMix64 step of c (Steele, Lea, Flood 2014): add the golden-ratio
+// increment, then two xor-shift-multiply rounds and a final xor-shift.
+// gfx950 executes the 32-bit multiplies of the 64-bit products at full VALU
+// rate, so one full hash is 18 VALU instructions.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t splitmix64(uint64_t c)
+{
+    uint64_t z = c + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Top 32 bits of the hash only: the low half of the last product and of the
+// final xor-shift are never formed.
+__device__ __forceinline__ uint32_t splitmix64_hi(uint64_t c)
+{
+    uint64_t z = c + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    uint32_t h = (uint32_t)(z >> 32);
+    return h ^ (h >> 31);
+}
+
+// ---------------------------------------------------------------------------
+// Output element types.  OutT is the storage type; the arithmetic is FP64 for
+// double output (the plain FP64 kernels) and FP32 otherwise.
+// ---------------------------------------------------------------------------
+struct bf16_t { uint16_t bits; };
+struct f16_t { uint16_t bits; };
+
+template <typename OutT> struct out_traits;
+template <> struct out_traits<double> { using math = double; static constexpr int bytes = 8; };
+template <> struct out_traits<float> { using math = float; static constexpr int bytes = 4; };
+template <> struct out_traits<bf16_t> { using math = float; static constexpr int bytes = 2; };
+template <> struct out_traits<f16_t> { using math = float; static constexpr int bytes = 2; };
+
+// Round-to-nearest-even float -> bfloat16 (values here are always finite).
+__device__ __forceinline__ uint16_t f32_to_bf16_bits(float f)
+{
+    uint32_t b = __float_as_uint(f);
+    b += 0x7FFFu + ((b >> 16) & 1u);
+    return (uint16_t)(b >> 16);
+}
+
+// Round-to-nearest-even float -> binary16 (hardware conversion; subnormal
+// halves are kept).
+__device__ __forceinline__ uint16_t f32_to_f16_bits(float f)
+{
+    _Float16 h = (_Float16)f;
+    return __builtin_bit_cast(uint16_t, h);
+}
+
+template <typename OutT> __device__ __forceinline__ uint16_t to_bits16(float f);
+template <> __device__ __forceinline__ uint16_t to_bits16<bf16_t>(float f) { return f32_to_bf16_bits(f); }
+template <> __device__ __forceinline__ uint16_t to_bits16<f16_t>(float f) { return f32_to_f16_bits(f); }
+
+// Store one element.
+template <typename OutT> __device__ __forceinline__ void store1(OutT* p, typename out_traits<OutT>::math v);
+template <> __device__ __forceinline__ void store1<double>(double* p, double v) { *p = v; }
+template <> __device__ __forceinline__ void store1<float>(float* p, float v) { *p = v; }
+template <> __device__ __forceinline__ void store1<bf16_t>(bf16_t* p, float v) { ((uint16_t*)p)[0] = f32_to_bf16_bits(v); }
+template <> __device__ __forceinline__ void store1<f16_t>(f16_t* p, float v) { ((uint16_t*)p)[0] = f32_to_f16_bits(v); }
+
+// Store a pair (x, y) at p[0], p[1]; one 2-element store when p is aligned to
+// the pair size, otherwise two element stores.
+template <typename OutT>
+__device__ __forceinline__ void store_pair(OutT* p, typename out_traits<OutT>::math x,
+                                           typename out_traits<OutT>::math y)
+{
+    constexpr int B = out_traits<OutT>::bytes;
+    if ((reinterpret_cast<uintptr_t>(p) & (2 * B - 1)) == 0) {
+        if constexpr (B == 8) {
+            typedef double d2 __attribute__((ext_vector_type(2)));
+            *reinterpret_cast<d2*>(p) = d2{x, y};
+        } else if constexpr (B == 4) {
+            typedef float f2 __attribute__((ext_vector_type(2)));
+            *reinterpret_cast<f2*>(p) = f2{x, y};
+        } else {
+            uint32_t w = (uint32_t)to_bits16<OutT>(x) | ((uint32_t)to_bits16<OutT>(y) << 16);
+            *reinterpret_cast<uint32_t*>(p) = w;
+        }
+    } else {
+        store1<OutT>(p, x);
+        store1<OutT>(p + 1, y);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Conversions of 64-bit integers to float with relative error below 2^-23
+// (the high word is converted and scaled, the low word added by an FMA).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float u64_to_f32_scaled(uint64_t q, float scale_hi, float scale_lo)
+{
+    float hi = (float)(uint32_t)(q >> 32);
+    float lo = (float)(uint32_t)q;
+    return __builtin_fmaf(hi, scale_hi, lo * scale_lo);
+}
+
+// ---------------------------------------------------------------------------
+// Algorithm B1 (Section 2): r = sigma sqrt(-2 ln(1 - u)), x = r sin(2 pi v) + mu,
+// y = r cos(2 pi v) + mu, with u = (ku >> 11) 2^-53 and v = (kv >> 11) 2^-53.
+// ---------------------------------------------------------------------------
+
+// FP64 evaluation, in the order of the algorithm with no fused operations:
+// 1 - u is exact, the angle is the rounded product (2 pi) v.
+__device__ __forceinline__ void b1_pair_f64(uint64_t ku, uint64_t kv, double mu, double sigma, double& x,
+                                            double& y)
+{
+    double u = (double)(ku >> 11) * 0x1p-53;
+    double v = (double)(kv >> 11) * 0x1p-53;
+    double r = __dmul_rn(sigma, sqrt(__dmul_rn(-2.0, log(__dsub_rn(1.0, u)))));
+    double t = __dmul_rn(2.0 * 3.141592653589793115997963, v);   // 2 fl(pi), exact doubling
+    double s, c;
+    sincos(t, &s, &c);
+    x = __dadd_rn(__dmul_rn(r, s), mu);
+    y = __dadd_rn(__dmul_rn(r, c), mu);
+}
+
+// FP32 evaluation.
+//  * ln(1 - u) with full relative accuracy for every u: with t = u 2^64 (the
+//    53 significant bits of the hash) and q = t for u < 1/2, q = 2^64 - t
+//    (= (1 - u) 2^64, exact) otherwise, qf = q 2^-64 rounded once.  For
+//    u >= 1/2, ln(1 - u) = ln(qf) directly.  For u < 1/2, y = 1 - qf is
+//    rounded; the exact remainder d = (1 - y) - qf (two exact operations)
+//    gives ln(1 - u) = ln(y) + ln(1 + d/y) ~= ln(y) + d (2 - y); |d| <= 2^-25,
+//    so replacing 1/y by 2 - y (error (1-y)^2/y) costs at most 2^-26 in
+//    absolute terms, about 0.2 ulp of |ln(1 - u)| >= 0.69 where it is
+//    largest.  One v_log_f32 in all cases.
+//  * The angle: v's top 32 bits read as a signed fraction of a turn give
+//    v - round(v) in [-1/2, 1/2) exactly; when it exceeds 1/4 in magnitude,
+//    half a turn is added (flipping the sign of sin and cos) so the float
+//    angle has absolute error at most 2^-27 turns.  v_sin_f32 / v_cos_f32
+//    take revolutions.
+//  * sigma is folded in as r = sqrt(log2(1 - u) * (-2 ln 2 sigma^2)).
+__device__ __forceinline__ void b1_pair_f32(uint64_t ku, uint32_t kv_hi, float mu, float k2, float& x,
+                                            float& y)
+{
+    const uint64_t t = ku & ~0x7FFull;
+    const bool lowhalf = t < 0x8000000000000000ull;
+    const uint64_t q = lowhalf ? t : (0ull - t);
+    const float qf = u64_to_f32_scaled(q, 0x1p-32f, 0x1p-64f);
+    const float yv = 1.0f - qf;
+    const float d = (1.0f - yv) - qf;
+    const float corr = lowhalf ? d * (2.0f - yv) : 0.0f;
+    const float arg = lowhalf ? yv : qf;
+    const float l2 = __builtin_fmaf(corr, 1.4426950408889634f, __builtin_amdgcn_logf(arg));  // log2(1 - u)
+    float r = __builtin_amdgcn_sqrtf(l2 * k2);
+
+    // a / 2^32 = v - round(v); flip when a lies outside [-2^30, 2^30)
+    const bool flip = (kv_hi + 0x40000000u) >= 0x80000000u;
+    const int32_t a = (int32_t)(flip ? (kv_hi ^ 0x80000000u) : kv_hi);
+    r = flip ? -r : r;
+    const float turns = (float)a * 0x1p-32f;
+    const float sn = __builtin_amdgcn_sinf(turns);
+    const float cs = __builtin_amdgcn_cosf(turns);
+    x = __builtin_fmaf(r, sn, mu);
+    y = __builtin_fmaf(r, cs, mu);
+}
+
+// ---------------------------------------------------------------------------
+// Algorithm P (Section 2).  Candidate (X, Y) of signed 32-bit integers,
+// x = X 2^-31, y = Y 2^-31, s = S 2^-62 with S = X^2 + Y^2 in uint64.
+// Accept iff 0 < S < 2^62 (s < 1 decided exactly; s = 0 rejected).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t polar_S(int32_t X, int32_t Y)
+{
+    uint32_t ax = (uint32_t)(X < 0 ? -(int64_t)X : (int64_t)X);
+    uint32_t ay = (uint32_t)(Y < 0 ? -(int64_t)Y : (int64_t)Y);
+    return (uint64_t)ax * ax + (uint64_t)ay * ay;
+}
+
+__device__ __forceinline__ bool polar_accept(uint64_t S)
+{
+    return S != 0 && S < (1ull << 62);
+}
+
+// FP64 value: s = RNE(S) 2^-62, r = sigma sqrt(-2 ln(s) / s), no fused ops.
+__device__ __forceinline__ void polar_value_f64(int32_t X, int32_t Y, uint64_t S, double mu, double sigma,
+                                                double& zx, double& zy)
+{
+    double s = __dmul_rn((double)S, 0x1p-62);
+    double r = __dmul_rn(sigma, sqrt(__ddiv_rn(__dmul_rn(-2.0, log(s)), s)));
+    zx = __dadd_rn(__dmul_rn(r, __dmul_rn((double)X, 0x1p-31)), mu);
+    zy = __dadd_rn(__dmul_rn(r, __dmul_rn((double)Y, 0x1p-31)), mu);
+}
+
+// FP32 value.
+//  * ln(s): for s <= 1/2, log2 of sf = S 2^-62 rounded once.  For s > 1/2,
+//    s = 1 - d with d = (2^62 - S) 2^-62 exact; y = 1 - df rounded and the
+//    exact remainder e = (1 - y) - df give ln(s) = ln(y) + e (2 - y), as in
+//    B1 above.  This keeps ln(s) accurate as s -> 1, where ln(s) cancels.
+//  * s < 2^-20 (S < 2^42): ln(s)/s is evaluated in FP64 (exact s; rare).
+//  * r = sqrt(log2(s) * (-2 ln 2 sigma^2) / s); z = r x + mu by an FMA.
+__device__ __forceinline__ void polar_value_f32(int32_t X, int32_t Y, uint64_t S, float mu, float k2,
+                                                float sigma, float& zx, float& zy)
+{
+    float r;
+    if (S < (1ull << 42)) {
+        double s = (double)S * 0x1p-62;                       // exact
+        double rd = sqrt(-2.0 * log(s) / s);
+        r = (float)rd * sigma;
+    } else {
+        const bool high = S > (1ull << 61);
+        const float sf = u64_to_f32_scaled(S, 0x1p-30f, 0x1p-62f);
+        const float df = u64_to_f32_scaled((1ull << 62) - S, 0x1p-30f, 0x1p-62f);
+        const float yv = 1.0f - df;
+        const float e = (1.0f - yv) - df;
+        const float arg = high ? yv : sf;
+        const float corr = high ? e * (2.0f - yv) : 0.0f;
+        const float l2 = __builtin_fmaf(corr, 1.4426950408889634f, __builtin_amdgcn_logf(arg));
+        r = __builtin_amdgcn_sqrtf(l2 * k2 * __builtin_amdgcn_rcpf(sf));
+    }
+    zx = __builtin_fmaf(r, (float)X * 0x1p-31f, mu);
+    zy = __builtin_fmaf(r, (float)Y * 0x1p-31f, mu);
+}
+
+// ---------------------------------------------------------------------------
+// Wavefront helpers (wave64).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
+
+// Number of set bits of m in lanes below this one.
+__device__ __forceinline__ uint32_t rank_below(uint64_t m)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        v += (uint64_t)__shfl_xor((unsigned long long)v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t v)
+{
+    uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// ---------------------------------------------------------------------------
+// Look-back status words (one per tile): [63:42] launch tag, [41:40] flag
+// (1 = tile aggregate, 2 = inclusive prefix), [39:0] accepted-pair count.
+// Accessed only with relaxed agent-scope atomics: the word carries all the
+// information, so no other memory needs to be ordered with it.
+// ---------------------------------------------------------------------------
+constexpr uint64_t ST_AGG = 1, ST_INC = 2;
+constexpr uint64_t ST_VAL_MASK = (1ull << 40) - 1;
+
+__device__ __forceinline__ uint64_t st_pack(uint32_t tag, uint64_t flag, uint64_t val)
+{
+    return ((uint64_t)tag << 42) | (flag << 40) | (val & ST_VAL_MASK);
+}
+
+__device__ __forceinline__ void st_publish(uint64_t* p, uint64_t w)
+{
+    __hip_atomic_store(p, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint64_t st_read(const uint64_t* p)
+{
+    return __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Exclusive prefix (accepted pairs before tile lt of a stream whose status
+// words start at st0), by decoupled look-back over windows of 64
+// predecessors read in parallel by one wave.  Predecessor words go from
+// invalid to aggregate to inclusive; the window is summed once every word up
+// to the nearest inclusive one is valid.  Called by all 64 lanes of one wave.
+__device__ __forceinline__ uint64_t lookback(const uint64_t* st0, uint32_t lt, uint32_t tag)
+{
+    const uint32_t lane = lane_id();
+    uint64_t excl = 0;
+    int64_t pos = (int64_t)lt - 1;
+    for (;;) {
+        const int64_t li = pos - (int64_t)lane;
+        bool valid = true, inc = true;
+        uint64_t val = 0;
+        if (li >= 0) {
+            const uint64_t w = st_read(st0 + li);
+            valid = (uint32_t)(w >> 42) == tag && ((w >> 40) & 3) != 0;
+            inc = ((w >> 40) & 3) == ST_INC;
+            val = w & ST_VAL_MASK;
+        }
+        const uint64_t vmask = __ballot(valid);
+        const uint64_t imask = __ballot(valid && inc);
+        const int first = imask ? (int)__builtin_ctzll(imask) : 64;
+        const uint64_t need = first >= 63 ? ~0ull : ((2ull << first) - 1);
+        if ((vmask & need) == need) {
+            excl += wave_sum_u64((int)lane <= first ? val : 0);
+            if (first < 64)
+                return excl;
+            pos -= 64;
+        } else {
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+}
+
+}  // namespace nrng

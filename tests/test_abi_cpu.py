@@ -1,0 +1,95 @@
+"""Host-only checks of the C ABI (no GPU): the library loads, exports every
+entry point that include/nrng.h declares, and rejects bad arguments before
+touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1004_3105_amd import binding as nb
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "nrng.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(nrng_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_expected_entry_points():
+    fns = header_functions()
+    for name in ("nrng_boxmuller", "nrng_polar", "nrng_batched", "nrng_polar_dev", "nrng_strerror"):
+        assert name in fns
+
+
+def test_library_exports_every_declared_symbol():
+    L = nb.lib()
+    missing = [f for f in header_functions() if not hasattr(L, f)]
+    assert not missing, missing
+    # and the binding wraps each of them under the same name
+    assert sorted(header_functions()) == nb.EXPORTED
+    for f in header_functions():
+        assert callable(getattr(nb, f))
+
+
+def test_strerror_and_version():
+    L = nb.lib()
+    for code in range(-7, 1):
+        assert isinstance(L.nrng_strerror(code), bytes) and len(L.nrng_strerror(code)) > 0
+    assert L.nrng_strerror(-99) == b"unknown status"
+    assert L.nrng_version() >= 10000
+
+
+def test_argument_errors_return_before_any_launch():
+    L = nb.lib()
+    p = ctypes.c_void_p(0x1000)   # never dereferenced: every call below fails validation first
+    # unknown dtype
+    assert L.nrng_boxmuller(1, 0, 10, 0.0, 1.0, p, 7, None) == nb.NRNG_EDTYPE
+    assert L.nrng_polar(1, 0, 10, 0.0, 1.0, p, -1, None, None) == nb.NRNG_EDTYPE
+    assert L.nrng_batched(0, 4, p, p, p, None, p, p, p, 100, 9, None, None) == nb.NRNG_EDTYPE
+    # bad mu / sigma
+    for mu, sigma in ((0.0, -1.0), (float("nan"), 1.0), (0.0, float("inf")), (float("-inf"), 1.0)):
+        assert L.nrng_boxmuller(1, 0, 10, mu, sigma, p, 1, None) == nb.NRNG_EINVAL
+        assert L.nrng_polar(1, 0, 10, mu, sigma, p, 1, None, None) == nb.NRNG_EINVAL
+        assert L.nrng_test_b1_words(p, 4, mu, sigma, p, 1, None) == nb.NRNG_EINVAL
+    # null output with n > 0
+    assert L.nrng_boxmuller(1, 0, 10, 0.0, 1.0, None, 1, None) == nb.NRNG_EINVAL
+    assert L.nrng_polar(1, 0, 10, 0.0, 1.0, None, 1, None, None) == nb.NRNG_EINVAL
+    assert L.nrng_polar_dev(1, None, 10, 0.0, 1.0, p, 1, None) == nb.NRNG_EINVAL
+    # n = 0 is a no-op
+    assert L.nrng_boxmuller(1, 0, 0, 0.0, 1.0, None, 1, None) == nb.NRNG_OK
+    assert L.nrng_polar(1, 0, 0, 0.0, 1.0, None, 1, None, None) == nb.NRNG_OK
+    # batched: bad method, zero streams, null arrays
+    assert L.nrng_batched(5, 4, p, p, p, None, p, p, p, 100, 1, None, None) == nb.NRNG_EINVAL
+    assert L.nrng_batched(0, 0, None, None, None, None, None, None, None, 0, 1, None, None) == nb.NRNG_OK
+    assert L.nrng_batched(1, 4, None, p, p, None, p, p, p, 100, 1, None, None) == nb.NRNG_EINVAL
+    assert L.nrng_batched(1, 4, p, p, p, None, p, p, None, 100, 1, None, None) == nb.NRNG_EINVAL
+    # sizes beyond the supported range
+    assert L.nrng_polar(1, 0, (1 << 41) + 1, 0.0, 1.0, p, 1, None, None) == nb.NRNG_ERANGE
+    # test hooks
+    assert L.nrng_test_polar_budget(1, 0, 10, 0.0, 1.0, p, 1, 0, None, None) == nb.NRNG_EINVAL
+    assert L.nrng_test_polar_xy(None, 8, 0.0, 1.0, p, 1, p, p, None) == nb.NRNG_EINVAL
+    assert L.nrng_polar_trace(1, 0, 64, None, p, None) == nb.NRNG_EINVAL
+    assert L.nrng_probe_store(p, 17, None) == nb.NRNG_EINVAL
+    # graph helpers
+    assert L.nrng_fillgraph_launch(None, None) == nb.NRNG_EINVAL
+    assert L.nrng_fillgraph_destroy(None) == nb.NRNG_OK
+
+
+def test_tune_table_validation():
+    L = nb.lib()
+    assert nb.nrng_tune_variants(nb.KERNEL_POLAR)
+    assert nb.nrng_tune_variants(nb.KERNEL_B1)
+    assert L.nrng_tune_set(1, 1, 257, 3, 0) == nb.NRNG_EINVAL
+    assert L.nrng_tune_set(7, 1, 256, 4, 0) == nb.NRNG_EINVAL
+    assert L.nrng_tune_set(1, 9, 256, 4, 0) == nb.NRNG_EDTYPE
+    wg, un, g = nb.nrng_tune_get(nb.KERNEL_POLAR, nb.NRNG_F32)
+    assert (wg, un) in nb.nrng_tune_variants(nb.KERNEL_POLAR)
+    nb.nrng_tune_set(nb.KERNEL_POLAR, nb.NRNG_F32, wg, un, g)
+
+
+def test_binding_raises_on_error_status():
+    with pytest.raises(nb.NrngError):
+        nb.nrng_boxmuller(1, 0, 10, 0.0, -1.0, 0x1000, nb.NRNG_F32, 0)

@@ -1,0 +1,185 @@
+"""Batched streams in one persistent launch, and repeated fills through a
+HIP graph with a device-resident counter offset, against single-stream
+calls (bit-exact) and the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import synth
+from gpu_util import TDT, assert_close, case, dev, host, run, u64
+from paper_1004_3105_amd import binding as nb
+
+pytestmark = pytest.mark.gpu
+
+U64MAX = (1 << 64) - 1
+
+
+def to_dev(cfg, d):
+    return {
+        "seed": torch.from_numpy(cfg["seed"].view(np.int64)).to(d),
+        "offset": torch.from_numpy(cfg["offset"].view(np.int64)).to(d),
+        "n": torch.from_numpy(cfg["n"].view(np.int64)).to(d),
+        "mu": torch.from_numpy(cfg["mu"]).to(d),
+        "sigma": torch.from_numpy(cfg["sigma"]).to(d),
+    }
+
+
+def small_config(nstreams=97):
+    cfg = synth.batched_streams(nstreams=nstreams, seed=0x5EED, n_lo=1, n_hi=2e4)
+    cfg["n"][3] = 0          # an empty stream
+    cfg["n"][5] = 1          # a single value
+    cfg["offset"] = synth.rng(3).integers(0, 1 << 40, nstreams, dtype=np.uint64)
+    cfg["out_off"] = np.concatenate([[0], np.cumsum(cfg["n"][:-1])]).astype(np.uint64)
+    cfg["total"] = int(cfg["n"].sum())
+    return cfg
+
+
+@pytest.mark.parametrize("method", [nb.NRNG_METHOD_B1, nb.NRNG_METHOD_POLAR])
+@pytest.mark.parametrize("dtype", [nb.NRNG_F64, nb.NRNG_F32, nb.NRNG_BF16])
+def test_batched_packed_matches_single_streams(method, dtype):
+    d = dev()
+    cfg = small_config()
+    D = to_dev(cfg, d)
+    out = torch.full((cfg["total"],), float("nan"), dtype=TDT[dtype], device=d)
+    cons = torch.zeros(len(cfg["n"]), dtype=torch.int64, device=d)
+    case("batched packed", method, dtype, len(cfg["n"]), cfg["total"])
+    nb.nrng_batched(method, len(cfg["n"]), D["seed"], D["offset"], D["n"], None, D["mu"], D["sigma"], out,
+                    cfg["total"], dtype, None, cons)
+    torch.cuda.synchronize()
+    c = u64(cons)
+    name = "b1" if method == nb.NRNG_METHOD_B1 else "polar"
+    for j in range(len(cfg["n"])):
+        n = int(cfg["n"][j])
+        o0 = int(cfg["out_off"][j])
+        seg = out[o0:o0 + n]
+        single, used = run(name, int(cfg["seed"][j]), int(cfg["offset"][j]), n, dtype, float(cfg["mu"][j]),
+                           float(cfg["sigma"][j]), with_consumed=True)
+        assert torch.equal(seg, single), j
+        if name == "b1":
+            assert c[j] == 2 * ((n + 1) // 2)
+        elif n > 0:
+            assert c[j] == used, j
+        else:
+            assert c[j] == 0
+        if j % 8 == 0 and n > 0:
+            fn = O.b1 if name == "b1" else O.polar
+            ref, uref = fn(int(cfg["seed"][j]), int(cfg["offset"][j]), n, float(cfg["mu"][j]),
+                           float(cfg["sigma"][j]))
+            assert c[j] == uref
+            assert_close(host(seg), ref, dtype, float(cfg["mu"][j]), float(cfg["sigma"][j]),
+                         what="batched stream %d" % j)
+
+
+@pytest.mark.parametrize("method", [nb.NRNG_METHOD_B1, nb.NRNG_METHOD_POLAR])
+def test_batched_explicit_offsets_and_invalid_streams(method):
+    d = dev()
+    cfg = small_config(33)
+    n = cfg["n"]
+    # gaps of 0..3 elements between streams, so starts have every alignment
+    gaps = synth.rng(9).integers(0, 4, len(n)).astype(np.uint64)
+    off = np.zeros(len(n), dtype=np.uint64)
+    pos = 0
+    for j in range(len(n)):
+        pos += int(gaps[j])
+        off[j] = pos
+        pos += int(n[j])
+    out_len = pos
+    # stream 7 now points past the end of the buffer: it must be skipped
+    off[7] = out_len - int(n[7]) + 1 if n[7] > 0 else out_len + 1
+    D = to_dev(cfg, d)
+    doff = torch.from_numpy(off.view(np.int64)).to(d)
+    out = torch.full((out_len,), -777.0, dtype=torch.float32, device=d)
+    cons = torch.zeros(len(n), dtype=torch.int64, device=d)
+    case("batched explicit offsets", method)
+    nb.nrng_batched(method, len(n), D["seed"], D["offset"], D["n"], doff, D["mu"], D["sigma"], out, out_len,
+                    nb.NRNG_F32, None, cons)
+    torch.cuda.synchronize()
+    c = u64(cons)
+    assert c[7] == U64MAX
+    name = "b1" if method == nb.NRNG_METHOD_B1 else "polar"
+    written = torch.zeros(out_len, dtype=torch.bool, device=d)
+    for j in range(len(n)):
+        if j == 7:
+            continue
+        o0, nj = int(off[j]), int(n[j])
+        single = run(name, int(cfg["seed"][j]), int(cfg["offset"][j]), nj, nb.NRNG_F32, float(cfg["mu"][j]),
+                     float(cfg["sigma"][j]))
+        assert torch.equal(out[o0:o0 + nj], single), j
+        written[o0:o0 + nj] = True
+    # gaps and the skipped stream's range are untouched (except where a
+    # valid stream overlaps them)
+    assert torch.all(out[~written] == -777.0)
+
+
+def test_batched_overflowing_total_is_rejected_on_device():
+    d = dev()
+    cfg = small_config(16)
+    D = to_dev(cfg, d)
+    total = cfg["total"]
+    out_len = total - 1 - int(cfg["n"][-1]) // 2
+    out = torch.zeros(max(out_len, 1), dtype=torch.float32, device=d)
+    cons = torch.zeros(16, dtype=torch.int64, device=d)
+    case("batched packed overflow")
+    nb.nrng_batched(nb.NRNG_METHOD_POLAR, 16, D["seed"], D["offset"], D["n"], None, D["mu"], D["sigma"], out,
+                    out_len, nb.NRNG_F32, None, cons)
+    torch.cuda.synchronize()
+    c = u64(cons)
+    # packed layout: the streams that fit are produced, the last one is skipped
+    assert c[-1] == U64MAX
+    assert all(x != U64MAX for x in c[:-1])
+
+
+def test_fillgraph_repeated_fills_continue_one_stream():
+    d = dev()
+    n = (1 << 20) + 5
+    s = torch.cuda.Stream()
+    cursor = torch.zeros(1, dtype=torch.int64, device=d)
+    out = torch.empty(n, dtype=torch.float32, device=d)
+    nb.nrng_reserve(n, 0)
+    case("fillgraph create", n)
+    g = nb.nrng_fillgraph_create(7, cursor, n, 0.0, 1.0, out, nb.NRNG_F32, s)
+    try:
+        off = 0
+        for f in range(6):
+            case("fillgraph replay", f)
+            nb.nrng_fillgraph_launch(g, s)
+            s.synchronize()
+            ref, used = O.polar(7, off, n)
+            off += used
+            assert int(cursor.item()) == off, f
+            assert_close(host(out), ref, nb.NRNG_F32, what="fill %d" % f)
+            # eager work between replays
+            torch.cuda.synchronize()
+            x = torch.randn(1000, device=d).sum()
+            torch.cuda.synchronize()
+            del x
+    finally:
+        nb.nrng_fillgraph_destroy(g)
+
+
+def test_polar_dev_under_torch_graph_capture():
+    d = dev()
+    n = 50001
+    cursor = torch.zeros(1, dtype=torch.int64, device=d)
+    out = torch.empty(n, dtype=torch.float64, device=d)
+    nb.nrng_reserve(n, 0)
+    # warm-up call outside capture (library state initialised)
+    nb.nrng_polar_dev(3, cursor, n, 0.0, 1.0, out, nb.NRNG_F64)
+    torch.cuda.synchronize()
+    off = int(cursor.item())
+    g = torch.cuda.CUDAGraph()
+    case("torch graph capture nrng_polar_dev")
+    with torch.cuda.graph(g):
+        nb.nrng_polar_dev(3, cursor, n, 0.0, 1.0, out, nb.NRNG_F64)
+    for r in range(4):
+        case("torch graph replay", r)
+        g.replay()
+        torch.cuda.synchronize()
+        ref, used = O.polar(3, off, n)
+        off += used
+        assert int(cursor.item()) == off
+        assert_close(host(out), ref, nb.NRNG_F64, what="replay %d" % r)
+        y = torch.ones(10, device=d) * r
+        torch.cuda.synchronize()
+        del y
