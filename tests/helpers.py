@@ -65,6 +65,17 @@ def fp32_tol(z_ref: np.ndarray, mu, sigma) -> np.ndarray:
     return 2e-6 * scale
 
 
+def fp64_scaled_tol(z_ref: np.ndarray, mu, sigma) -> np.ndarray:
+    """FP64 bar for z = sigma n + mu: 4 ulp of max(|z|, |mu|, sigma |n|)."""
+    z = np.abs(z_ref)
+    mu = np.asarray(mu, dtype=np.float64)
+    sigma = np.asarray(sigma, dtype=np.float64)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        nref = np.where(sigma > 0, (z_ref - mu) / np.where(sigma > 0, sigma, 1.0), 0.0)
+    scale = np.maximum.reduce([z, np.abs(mu) * np.ones_like(z), np.abs(sigma * nref)])
+    return 4.0 * np.spacing(scale)
+
+
 def ulp_of(x: np.ndarray, dtype) -> np.ndarray:
     """Spacing of the target format at |x| (normal and subnormal range)."""
     x = np.abs(np.asarray(x, dtype=np.float64))
