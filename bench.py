@@ -1,0 +1,321 @@
+#!/usr/bin/env python3
+"""Benchmark of the normal-deviate hot path on one MI355X.
+
+One step = the batched workload (4096 streams, lengths log-uniform on
+[1e2, 1e6], per-stream mu, sigma and seed; about 4.45e8 normals per method)
+turned into FP32 normals by Box-Muller (Algorithm B1) AND by the Polar method
+(Algorithm P), each as one tile-table set-up kernel plus one persistent
+kernel, through the C ABI.  The printed `value` is the whole step's
+throughput in normals per second (both methods' normals over the step time),
+with every input resident in GPU memory before timing starts.
+
+Alongside, outside the timed region: the measured store-only and hash-only
+ceilings, the single-stream fills of 2^30 normals (FP32, BF16, FP16 and the
+plain FP64 kernels, the comparison point of the FP32 batched figure), the
+graph-replayed repeated fill (64 x 2^28 Polar normals), and the CPU oracle
+timed on the host cores.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extras]
+                       [--no-cpu] [--only b1|polar]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "normals/s and % HBM write peak, FP32 batched vs plain FP64 (B1, Polar)"
+HBM_PEAK_GBS = 8000.0          # MI355X datasheet HBM3E bandwidth
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("nrng_kernels.hip", "nrng_device.hpp"):
+        with open(os.path.join(ROOT, "paper_1004_3105_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(kernel_tag: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary of
+    this kernel, if it was taken on the current kernel source."""
+    path = os.path.join(PROFILES, "traffic_%s.txt" % kernel_tag)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as f:
+        for line in f:
+            if "=" in line and not line.startswith("#"):
+                k, v = line.split("=", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("source_hash") != kernel_source_hash():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def median(xs):
+    xs = sorted(xs)
+    return xs[len(xs) // 2]
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--nstreams", type=int, default=4096)
+    ap.add_argument("--no-extras", action="store_true", help="skip the side measurements")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--only", choices=["b1", "polar"], default=None,
+                    help="time one method only (for profiling runs)")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="also run a 1 GiB copy and a 1 GiB store probe once (known traffic, for scaling "
+                         "hardware byte counters in profiling runs)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus %d, WORLD_SIZE %d requested)" % (args.gpus, world), file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1004_3105_amd import binding as nb
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    nb.nrng_init()
+    stream = torch.cuda.current_stream()
+
+    # ---------------------------------------------------------------- workload
+    cfg = synth.batched_streams(nstreams=args.nstreams)
+    ns = len(cfg["n"])
+    total = cfg["total"]
+    D = {
+        "seed": torch.from_numpy(cfg["seed"].view(np.int64)).to(dev),
+        "offset": torch.from_numpy(cfg["offset"].view(np.int64)).to(dev),
+        "n": torch.from_numpy(cfg["n"].view(np.int64)).to(dev),
+        "mu": torch.from_numpy(cfg["mu"]).to(dev),
+        "sigma": torch.from_numpy(cfg["sigma"]).to(dev),
+    }
+    methods = [("b1", nb.NRNG_METHOD_B1), ("polar", nb.NRNG_METHOD_POLAR)]
+    if args.only:
+        methods = [m for m in methods if m[0] == args.only]
+    outs = {name: torch.empty(total, dtype=torch.float32, device=dev) for name, _ in methods}
+    cons = {name: torch.zeros(ns, dtype=torch.int64, device=dev) for name, _ in methods}
+    nb.nrng_reserve(total, ns)
+
+    def step(evs=None):
+        k = 0
+        for name, m in methods:
+            if evs is not None:
+                evs[k].record(stream)
+            nb.nrng_batched_plan(m, ns, D["n"], None, total, nb.NRNG_F32, stream, cons[name])
+            if evs is not None:
+                evs[k + 1].record(stream)
+            nb.nrng_batched_exec(m, ns, D["seed"], D["offset"], D["n"], None, D["mu"], D["sigma"], outs[name],
+                                 nb.NRNG_F32, stream, cons[name])
+            k += 2
+        if evs is not None:
+            evs[k].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    nev = 2 * len(methods) + 1
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(nev)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        step(events[s])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    normals = total * len(methods) * args.steps
+    value = normals / elapsed
+    per_kernel = {}
+    for i, (name, _) in enumerate(methods):
+        plan_ms = [events[s][2 * i].elapsed_time(events[s][2 * i + 1]) for s in range(args.steps)]
+        exec_ms = [events[s][2 * i + 1].elapsed_time(events[s][2 * i + 2]) for s in range(args.steps)]
+        ms = sum(exec_ms) / len(exec_ms)
+        gbs = 4.0 * total / (ms * 1e-3) / 1e9
+        per_kernel[name] = {"plan_ms": round(sum(plan_ms) / len(plan_ms), 5), "exec_ms": round(ms, 5),
+                            "exec_median_ms": round(median(exec_ms), 5),
+                            "normals_per_s": total / (ms * 1e-3), "write_GBps": round(gbs, 1),
+                            "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)}
+
+    # dominant kernel -> roofline
+    dom = max(per_kernel, key=lambda k: per_kernel[k]["exec_ms"])
+    tag = "batched_%s_f32" % dom
+    achieved = per_kernel[dom]["write_GBps"]
+    traffic = read_traffic(tag)
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "polar_kernel<float,MODE_BATCHED>" if dom == "polar" else "b1_batched_kernel<float>",
+                "algorithmic_bytes_per_launch": 4 * total}
+
+    result = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "normals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "batched %d streams, B1 + Polar, FP32 out" % ns if len(methods) == 2 else
+                   "batched %d streams, %s only, FP32 out" % (ns, methods[0][0]),
+                   "nstreams": ns, "normals_per_method": total,
+                   "lengths": "log-uniform on [1e2, 1e6]", "mu": "U(-10, 10)", "sigma": "U(0.1, 5)",
+                   "seed_source": "PCG64(0xBA7C4)", "parallelism": "single GPU"},
+        "hbm_write_frac": round(4.0 * normals / elapsed / 1e9 / HBM_PEAK_GBS, 4),
+        "kernels": per_kernel,
+        "roofline": roofline,
+    }
+
+    if args.calibrate:
+        nbytes = 1 << 30
+        src = torch.empty(nbytes // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty(nbytes // 4, dtype=torch.float32, device=dev)
+        nb.nrng_probe_store(src, nbytes, stream)
+        nb.nrng_probe_copy(dst, src, nbytes, stream)
+        torch.cuda.synchronize()
+        result["calibration"] = {"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "store_bytes": nbytes}
+        del src, dst
+    if not args.no_extras:
+        result["extras"] = extras(nb, torch, dev, stream, per_kernel, value)
+    if not args.no_cpu:
+        result["cpu_baseline"] = cpu_baseline(cfg, [m for m, _ in methods])
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+def extras(nb, torch, dev, stream, per_kernel, batched_value):
+    """Side measurements (not part of the timed step)."""
+    ex = {}
+
+    def timed(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            fn()
+            b.record(stream)
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(b))
+        return median(ts)
+
+    # store-only and hash-only ceilings
+    nbytes = 4 << 30
+    buf = torch.empty(nbytes // 4, dtype=torch.float32, device=dev)
+    ms = timed(lambda: nb.nrng_probe_store(buf, nbytes, stream), 10)
+    ex["store_ceiling_GBps"] = round(nbytes / (ms * 1e-3) / 1e9, 1)
+    sink = torch.empty(256 * 2048, dtype=torch.int64, device=dev)
+    nh = 1 << 33
+    ms = timed(lambda: nb.nrng_probe_hash(1, nh, sink, sink.numel(), stream), 5)
+    ex["hash_ceiling_per_s"] = nh / (ms * 1e-3)
+
+    # single-stream fills of 2^30 normals (FP32 / BF16 / FP16 / plain FP64)
+    n = 1 << 30
+    single = {}
+    for name, dt, nbytes_el in (("f32", nb.NRNG_F32, 4), ("bf16", nb.NRNG_BF16, 2), ("f16", nb.NRNG_F16, 2),
+                                ("f64", nb.NRNG_F64, 8)):
+        out = torch.empty(n * nbytes_el // 4, dtype=torch.float32, device=dev)
+        nb.nrng_reserve(n, 0)
+        r = {}
+        ms = timed(lambda: nb.nrng_boxmuller(1, 0, n, 0.0, 1.0, out, dt, stream), 5)
+        r["b1_normals_per_s"] = n / (ms * 1e-3)
+        r["b1_write_GBps"] = round(n * nbytes_el / (ms * 1e-3) / 1e9, 1)
+        ms = timed(lambda: nb.nrng_polar(7, 0, n, 0.0, 1.0, out, dt, stream, None), 5)
+        r["polar_normals_per_s"] = n / (ms * 1e-3)
+        r["polar_write_GBps"] = round(n * nbytes_el / (ms * 1e-3) / 1e9, 1)
+        single[name] = r
+        del out
+        torch.cuda.empty_cache()
+    ex["single_stream_2^30"] = single
+    f64 = single["f64"]
+    ex["fp32_batched_vs_plain_fp64"] = {
+        "b1": per_kernel["b1"]["normals_per_s"] / f64["b1_normals_per_s"] if "b1" in per_kernel else None,
+        "polar": per_kernel["polar"]["normals_per_s"] / f64["polar_normals_per_s"] if "polar" in per_kernel else None,
+        "step_vs_mean_fp64": batched_value / (0.5 * (f64["b1_normals_per_s"] + f64["polar_normals_per_s"])),
+    }
+
+    # repeated fill: 64 graph replays of a 2^28 FP32 Polar fill
+    nf = 1 << 28
+    out = torch.empty(nf, dtype=torch.float32, device=dev)
+    cursor = torch.zeros(1, dtype=torch.int64, device=dev)
+    side = torch.cuda.Stream()
+    g = nb.nrng_fillgraph_create(7, cursor, nf, 0.0, 1.0, out, nb.NRNG_F32, side)
+    try:
+        nb.nrng_fillgraph_launch(g, side)
+        side.synchronize()
+        cursor.zero_()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(side)
+        for _ in range(64):
+            nb.nrng_fillgraph_launch(g, side)
+        b.record(side)
+        side.synchronize()
+        ms = a.elapsed_time(b)
+    finally:
+        nb.nrng_fillgraph_destroy(g)
+    ex["graph_fill_64x2^28"] = {"ms_total": round(ms, 3), "normals_per_s": 64 * nf / (ms * 1e-3),
+                               "write_GBps": round(64 * nf * 4 / (ms * 1e-3) / 1e9, 1),
+                               "cursor_after": int(cursor.item())}
+    return ex
+
+
+def cpu_baseline(cfg, methods):
+    """The FP64 oracle over every stream of the same batched workload, one
+    oracle call per stream, spread over the host cores."""
+    import numpy as np  # noqa: F401
+    from concurrent.futures import ThreadPoolExecutor
+
+    import oracle as O
+    O.lib()
+    cores = min(16, os.cpu_count() or 1)
+    ns = len(cfg["n"])
+    jobs = [(m, j) for m in methods for j in range(ns)]
+
+    def work(mj):
+        m, j = mj
+        fn = O.b1 if m == "b1" else O.polar
+        fn(int(cfg["seed"][j]), int(cfg["offset"][j]), int(cfg["n"][j]), float(cfg["mu"][j]), float(cfg["sigma"][j]))
+        return int(cfg["n"][j])
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=cores) as ex:
+        done = sum(ex.map(work, jobs, chunksize=8))
+    dt = time.perf_counter() - t0
+    return {"value": done / dt, "unit": "normals/s", "cores": cores, "kind": "oracle",
+            "sample": "the whole batched workload: %d streams x %s, %d normals, one FP64 oracle call per "
+                      "stream on a %d-thread pool (%.1f s wall)" % (ns, "+".join(methods), done, cores, dt)}
+
+
+if __name__ == "__main__":
+    sys.exit(main())

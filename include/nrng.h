@@ -156,6 +156,23 @@ int nrng_batched(int method, uint32_t nstreams, const uint64_t *d_seed, const ui
                  const uint64_t *d_n, const uint64_t *d_out_off, const double *d_mu, const double *d_sigma,
                  void *out, uint64_t out_len, int dtype, void *stream, uint64_t *d_consumed);
 
+/* The two halves of nrng_batched, for callers that refill the same set of
+ * streams repeatedly or time the main kernel on its own.
+ * nrng_batched_plan builds the tile table of the batch in the device
+ * workspace (one small kernel; d_consumed as in nrng_batched, written for
+ * skipped and empty streams and for every B1 stream); nrng_batched_exec runs
+ * the persistent kernel over the most recent plan of this device.  exec
+ * returns NRNG_EINVAL unless the latest plan was made for the same method,
+ * dtype, launch variant, stream count and layout (packed or not); d_n and
+ * d_out_off must hold the values the plan saw.  A plan stays valid until the
+ * next plan or batched call on the device.  nrng_batched(...) is
+ * plan + exec. */
+int nrng_batched_plan(int method, uint32_t nstreams, const uint64_t *d_n, const uint64_t *d_out_off,
+                      uint64_t out_len, int dtype, void *stream, uint64_t *d_consumed);
+int nrng_batched_exec(int method, uint32_t nstreams, const uint64_t *d_seed, const uint64_t *d_offset,
+                      const uint64_t *d_n, const uint64_t *d_out_off, const double *d_mu, const double *d_sigma,
+                      void *out, int dtype, void *stream, uint64_t *d_consumed);
+
 /* ------------------------------------------------------------------------
  * Repeated fills through a HIP graph: capture one nrng_polar_dev launch
  * (with the workspace reserved beforehand) and return an instantiated graph

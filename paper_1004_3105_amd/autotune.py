@@ -1,0 +1,132 @@
+"""Autotuner for the launch configuration of the nrng kernels.
+
+For each kernel (B1 single stream, Polar, B1 batched) and output dtype it
+times every compiled (workgroup size, unroll) variant at a few persistent-
+grid caps on a representative workload, keeps the fastest, and writes the
+table to tune_<arch>.json next to this file.  `apply()` loads such a table
+into the library (nrng_tune_set); the binding calls it on first use.
+
+Usage (on the GPU): python -m paper_1004_3105_amd.autotune [--quick]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+
+from . import binding as nb
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KNAME = {nb.KERNEL_B1: "b1", nb.KERNEL_POLAR: "polar", nb.KERNEL_B1_BATCHED: "b1_batched"}
+DNAME = {nb.NRNG_F64: "f64", nb.NRNG_F32: "f32", nb.NRNG_BF16: "bf16", nb.NRNG_F16: "f16"}
+
+
+def table_path(arch: str = "gfx950") -> str:
+    return os.path.join(HERE, "tune_%s.json" % arch)
+
+
+def apply(path: str | None = None) -> bool:
+    """Load a tune table into the library; False if there is none."""
+    path = path or table_path()
+    if not os.path.exists(path):
+        return False
+    with open(path) as f:
+        tab = json.load(f)
+    inv_k = {v: k for k, v in KNAME.items()}
+    inv_d = {v: k for k, v in DNAME.items()}
+    for e in tab.get("entries", []):
+        nb.nrng_tune_set(inv_k[e["kernel"]], inv_d[e["dtype"]], e["wg"], e["unroll"], e.get("grid_per_cu", 0))
+    return True
+
+
+def _time(torch, fn, reps):
+    fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
+def tune(quick: bool = False, out_path: str | None = None, log=print) -> dict:
+    import numpy as np
+    import torch
+
+    import synth
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    nb.nrng_init()
+    reps = 3 if quick else 7
+    n = 1 << (26 if quick else 28)
+    cfg = synth.batched_streams(nstreams=1024 if quick else 4096)
+    ns, total = len(cfg["n"]), cfg["total"]
+    D = {k: torch.from_numpy(cfg[k].view(np.int64) if cfg[k].dtype == np.uint64 else cfg[k]).to(dev)
+         for k in ("seed", "offset", "n", "mu", "sigma")}
+    nb.nrng_reserve(max(n, total), ns)
+    entries = []
+    gpcs = [0, 1, 2, 4] if not quick else [0, 2]
+    for kernel in (nb.KERNEL_B1, nb.KERNEL_POLAR, nb.KERNEL_B1_BATCHED):
+        variants = nb.nrng_tune_variants(kernel)
+        for dtype in (nb.NRNG_F32, nb.NRNG_BF16, nb.NRNG_F16, nb.NRNG_F64):
+            esize = 8 if dtype == nb.NRNG_F64 else (4 if dtype == nb.NRNG_F32 else 2)
+            # the Polar timing writes both an n-element single stream and the
+            # total-element batch into `out`, so it holds max(n, total) elements
+            if kernel == nb.KERNEL_B1_BATCHED:
+                nel = total
+            elif kernel == nb.KERNEL_POLAR:
+                nel = max(n, total)
+            else:
+                nel = n
+            out = torch.empty((nel * esize + 3) // 4, dtype=torch.float32, device=dev)
+            saved = nb.nrng_tune_get(kernel, dtype)
+            results = []
+            for wg, un in variants:
+                for gpc in gpcs:
+                    nb.nrng_tune_set(kernel, dtype, wg, un, gpc)
+                    if kernel == nb.KERNEL_B1:
+                        fn = lambda: nb.nrng_boxmuller(1, 0, n, 0.0, 1.0, out, dtype)  # noqa: E731
+                        work = n
+                    elif kernel == nb.KERNEL_POLAR:
+                        # Polar's variant also drives the batched Polar kernel: time both
+                        def fn():
+                            nb.nrng_polar(7, 0, n, 0.0, 1.0, out, dtype)
+                            nb.nrng_batched(nb.NRNG_METHOD_POLAR, ns, D["seed"], D["offset"], D["n"], None,
+                                            D["mu"], D["sigma"], out, total, dtype)
+                        work = n + total
+                    else:
+                        fn = lambda: nb.nrng_batched(nb.NRNG_METHOD_B1, ns, D["seed"], D["offset"], D["n"],  # noqa
+                                                     None, D["mu"], D["sigma"], out, total, dtype)
+                        work = total
+                    ms = _time(torch, fn, reps)
+                    results.append((ms, wg, un, gpc))
+                    log("%-10s %-4s wg %4d unroll %2d grid/CU %d: %8.3f ms  %.3e normals/s" % (
+                        KNAME[kernel], DNAME[dtype], wg, un, gpc, ms, work / (ms * 1e-3)))
+            nb.nrng_tune_set(kernel, dtype, *saved)
+            best = min(results)
+            entries.append({"kernel": KNAME[kernel], "dtype": DNAME[dtype], "wg": best[1], "unroll": best[2],
+                            "grid_per_cu": best[3], "ms": round(best[0], 4)})
+            del out
+            torch.cuda.empty_cache()
+    tab = {"arch": "gfx950", "n_single": n, "nstreams": ns, "entries": entries}
+    path = out_path or table_path()
+    with open(path, "w") as f:
+        json.dump(tab, f, indent=1)
+    return tab
+
+
+if __name__ == "__main__":
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--quick", action="store_true")
+    ap.add_argument("--out", default=None)
+    a = ap.parse_args()
+    t = tune(quick=a.quick, out_path=a.out, log=lambda s: print(s, flush=True))
+    json.dump(t, sys.stdout, indent=1)
+    print()

@@ -35,6 +35,8 @@ _SIGS = {
     "nrng_polar": (_i32, [_u64, _u64, _u64, _f64, _f64, _vp, _i32, _vp, _vp]),
     "nrng_polar_dev": (_i32, [_u64, _vp, _u64, _f64, _f64, _vp, _i32, _vp]),
     "nrng_batched": (_i32, [_i32, _u32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _u64, _i32, _vp, _vp]),
+    "nrng_batched_plan": (_i32, [_i32, _u32, _vp, _vp, _u64, _i32, _vp, _vp]),
+    "nrng_batched_exec": (_i32, [_i32, _u32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp]),
     "nrng_fillgraph_create": (_i32, [_u64, _vp, _u64, _f64, _f64, _vp, _i32, _vp, ctypes.POINTER(_vp)]),
     "nrng_fillgraph_launch": (_i32, [_vp, _vp]),
     "nrng_fillgraph_destroy": (_i32, [_vp]),
@@ -88,6 +90,21 @@ def _ptr(x):
     raise TypeError("expected a tensor, an int address or None, got %r" % type(x))
 
 
+_ESIZE = {NRNG_F64: 8, NRNG_F32: 4, NRNG_BF16: 2, NRNG_F16: 2}
+
+
+def _need(t, nbytes: int, what: str) -> None:
+    """When a buffer argument is a tensor, check that it holds nbytes bytes
+    (raw addresses cannot be checked and are trusted)."""
+    if t is None or isinstance(t, int) or not hasattr(t, "data_ptr"):
+        return
+    have = t.numel() * t.element_size()
+    if not t.is_contiguous():
+        raise ValueError("%s: contiguous tensor expected" % what)
+    if have < nbytes:
+        raise ValueError("%s: tensor holds %d bytes, the call writes or reads %d" % (what, have, nbytes))
+
+
 def _stream(s):
     if s is None:
         import torch
@@ -124,28 +141,56 @@ def nrng_reserve(max_n: int, max_streams: int = 0) -> None:
 
 
 def nrng_boxmuller(seed, offset, n, mu, sigma, out, dtype, stream=None) -> None:
+    _need(out, n * _ESIZE.get(dtype, 0), "nrng_boxmuller out")
     _check("nrng_boxmuller", lib().nrng_boxmuller(seed & (2**64 - 1), offset & (2**64 - 1), n, mu, sigma,
                                                   _ptr(out), dtype, _stream(stream)))
 
 
 def nrng_polar(seed, offset, n, mu, sigma, out, dtype, stream=None, d_consumed=None) -> None:
+    _need(out, n * _ESIZE.get(dtype, 0), "nrng_polar out")
+    _need(d_consumed, 8, "nrng_polar d_consumed")
     _check("nrng_polar", lib().nrng_polar(seed & (2**64 - 1), offset & (2**64 - 1), n, mu, sigma, _ptr(out),
                                           dtype, _stream(stream), _ptr(d_consumed)))
 
 
 def nrng_polar_dev(seed, d_cursor, n, mu, sigma, out, dtype, stream=None) -> None:
+    _need(out, n * _ESIZE.get(dtype, 0), "nrng_polar_dev out")
+    _need(d_cursor, 8, "nrng_polar_dev d_cursor")
     _check("nrng_polar_dev", lib().nrng_polar_dev(seed & (2**64 - 1), _ptr(d_cursor), n, mu, sigma, _ptr(out),
                                                   dtype, _stream(stream)))
 
 
 def nrng_batched(method, nstreams, d_seed, d_offset, d_n, d_out_off, d_mu, d_sigma, out, out_len, dtype,
                  stream=None, d_consumed=None) -> None:
+    _need(out, out_len * _ESIZE.get(dtype, 0), "nrng_batched out")
+    for t, nm in ((d_seed, "d_seed"), (d_offset, "d_offset"), (d_n, "d_n"), (d_out_off, "d_out_off"),
+                  (d_mu, "d_mu"), (d_sigma, "d_sigma"), (d_consumed, "d_consumed")):
+        _need(t, 8 * nstreams, "nrng_batched " + nm)
     _check("nrng_batched", lib().nrng_batched(method, nstreams, _ptr(d_seed), _ptr(d_offset), _ptr(d_n),
                                               _ptr(d_out_off), _ptr(d_mu), _ptr(d_sigma), _ptr(out), out_len,
                                               dtype, _stream(stream), _ptr(d_consumed)))
 
 
+def nrng_batched_plan(method, nstreams, d_n, d_out_off, out_len, dtype, stream=None, d_consumed=None) -> None:
+    for t, nm in ((d_n, "d_n"), (d_out_off, "d_out_off"), (d_consumed, "d_consumed")):
+        _need(t, 8 * nstreams, "nrng_batched_plan " + nm)
+    _check("nrng_batched_plan", lib().nrng_batched_plan(method, nstreams, _ptr(d_n), _ptr(d_out_off), out_len,
+                                                        dtype, _stream(stream), _ptr(d_consumed)))
+
+
+def nrng_batched_exec(method, nstreams, d_seed, d_offset, d_n, d_out_off, d_mu, d_sigma, out, dtype, stream=None,
+                      d_consumed=None) -> None:
+    for t, nm in ((d_seed, "d_seed"), (d_offset, "d_offset"), (d_n, "d_n"), (d_out_off, "d_out_off"),
+                  (d_mu, "d_mu"), (d_sigma, "d_sigma"), (d_consumed, "d_consumed")):
+        _need(t, 8 * nstreams, "nrng_batched_exec " + nm)
+    _check("nrng_batched_exec", lib().nrng_batched_exec(method, nstreams, _ptr(d_seed), _ptr(d_offset), _ptr(d_n),
+                                                        _ptr(d_out_off), _ptr(d_mu), _ptr(d_sigma), _ptr(out),
+                                                        dtype, _stream(stream), _ptr(d_consumed)))
+
+
 def nrng_fillgraph_create(seed, d_cursor, n, mu, sigma, out, dtype, stream) -> int:
+    _need(out, n * _ESIZE.get(dtype, 0), "nrng_fillgraph_create out")
+    _need(d_cursor, 8, "nrng_fillgraph_create d_cursor")
     h = _vp()
     _check("nrng_fillgraph_create", lib().nrng_fillgraph_create(seed & (2**64 - 1), _ptr(d_cursor), n, mu, sigma,
                                                                 _ptr(out), dtype, _stream(stream),
@@ -180,35 +225,49 @@ def nrng_tune_variants(kernel):
 
 
 def nrng_test_b1_words(d_words, npairs, mu, sigma, out, dtype, stream=None) -> None:
+    _need(d_words, 16 * npairs, "nrng_test_b1_words d_words")
+    _need(out, 2 * npairs * _ESIZE.get(dtype, 0), "nrng_test_b1_words out")
     _check("nrng_test_b1_words", lib().nrng_test_b1_words(_ptr(d_words), npairs, mu, sigma, _ptr(out), dtype,
                                                           _stream(stream)))
 
 
 def nrng_test_polar_xy(d_xy, ncand, mu, sigma, out, dtype, d_mask_words, d_count, stream=None) -> None:
+    _need(d_xy, 8 * ncand, "nrng_test_polar_xy d_xy")
+    _need(out, 2 * ncand * _ESIZE.get(dtype, 0), "nrng_test_polar_xy out")
+    _need(d_mask_words, 8 * ((ncand + 63) // 64), "nrng_test_polar_xy d_mask_words")
+    _need(d_count, 8, "nrng_test_polar_xy d_count")
     _check("nrng_test_polar_xy", lib().nrng_test_polar_xy(_ptr(d_xy), ncand, mu, sigma, _ptr(out), dtype,
                                                           _ptr(d_mask_words), _ptr(d_count), _stream(stream)))
 
 
 def nrng_polar_trace(seed, offset, ncand, d_mask_words, d_word_prefix, stream=None) -> None:
+    _need(d_mask_words, 8 * ((ncand + 63) // 64), "nrng_polar_trace d_mask_words")
+    _need(d_word_prefix, 8 * ((ncand + 63) // 64), "nrng_polar_trace d_word_prefix")
     _check("nrng_polar_trace", lib().nrng_polar_trace(seed & (2**64 - 1), offset & (2**64 - 1), ncand,
                                                       _ptr(d_mask_words), _ptr(d_word_prefix), _stream(stream)))
 
 
 def nrng_test_polar_budget(seed, offset, n, mu, sigma, out, dtype, tiles, stream=None, d_consumed=None) -> None:
+    _need(out, n * _ESIZE.get(dtype, 0), "nrng_test_polar_budget out")
+    _need(d_consumed, 8, "nrng_test_polar_budget d_consumed")
     _check("nrng_test_polar_budget", lib().nrng_test_polar_budget(seed & (2**64 - 1), offset & (2**64 - 1), n, mu,
                                                                   sigma, _ptr(out), dtype, tiles, _stream(stream),
                                                                   _ptr(d_consumed)))
 
 
 def nrng_probe_store(out, nbytes, stream=None) -> None:
+    _need(out, nbytes, "nrng_probe_store out")
     _check("nrng_probe_store", lib().nrng_probe_store(_ptr(out), nbytes, _stream(stream)))
 
 
 def nrng_probe_copy(dst, src, nbytes, stream=None) -> None:
+    _need(dst, nbytes, "nrng_probe_copy dst")
+    _need(src, nbytes, "nrng_probe_copy src")
     _check("nrng_probe_copy", lib().nrng_probe_copy(_ptr(dst), _ptr(src), nbytes, _stream(stream)))
 
 
 def nrng_probe_hash(seed, nhash, d_sink, sink_len, stream=None) -> None:
+    _need(d_sink, 8 * sink_len, "nrng_probe_hash d_sink")
     _check("nrng_probe_hash", lib().nrng_probe_hash(seed & (2**64 - 1), nhash, _ptr(d_sink), sink_len,
                                                     _stream(stream)))
 

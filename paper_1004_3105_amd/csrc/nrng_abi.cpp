@@ -23,11 +23,18 @@ struct DevState {
     Ctl *ctl = nullptr;
     uint64_t *status = nullptr;
     uint64_t status_cap = 0;
+    uint64_t *bst = nullptr;        // block status words
+    uint64_t bcap = 0;
     uint64_t *tile_start = nullptr;
+    uint64_t *block_start = nullptr;
     uint64_t *packed_off = nullptr;
     uint64_t stream_cap = 0;
     int occ_polar[4][4][8] = {};     // [mode][dtype][variant], 0 = not queried
     int occ_b1[2][4][8] = {};        // [batched][dtype][variant]
+    // the tile table currently in the workspace (from nrng_batched_plan)
+    int plan_method = -1, plan_dtype = -1, plan_vi = -1;
+    uint32_t plan_nstreams = 0;
+    bool plan_packed = false;
 };
 
 struct Tune {
@@ -92,29 +99,35 @@ int get_dev(DevState **out)
     return NRNG_OK;
 }
 
-// Grow the look-back status array to at least `tiles` words (zeroed).
-int ensure_status(DevState &d, uint64_t tiles, hipStream_t s)
+// Grow the look-back arrays to at least `tiles` tile words and `blocks`
+// block words (all zeroed).
+int ensure_status(DevState &d, uint64_t tiles, uint64_t blocks, hipStream_t s)
 {
-    if (tiles <= d.status_cap)
+    if (tiles <= d.status_cap && blocks <= d.bcap)
         return NRNG_OK;
     if (capturing(s))
         return NRNG_ECAPTURE;
-    if (tiles > (1ull << 36))
+    if (tiles > (1ull << 36) || blocks > (1ull << 36))
         return NRNG_ERANGE;
-    uint64_t cap = tiles + tiles / 4 + 1024;
+    const uint64_t cap = std::max<uint64_t>(tiles + tiles / 4 + 1024, d.status_cap);
+    const uint64_t bcap = std::max<uint64_t>(blocks + blocks / 4 + 256, d.bcap);
     if (hipDeviceSynchronize() != hipSuccess)
         return NRNG_EHIP;
-    if (d.status)
-        hipFree(d.status);
-    d.status = nullptr;
-    d.status_cap = 0;
-    if (hipMalloc(&d.status, cap * sizeof(uint64_t)) != hipSuccess)
+    for (uint64_t **p : {&d.status, &d.bst}) {
+        if (*p)
+            hipFree(*p);
+        *p = nullptr;
+    }
+    d.status_cap = d.bcap = 0;
+    const size_t sb = cap * kStatusStride * sizeof(uint64_t), bb = bcap * kStatusStride * sizeof(uint64_t);
+    if (hipMalloc(&d.status, sb) != hipSuccess || hipMalloc(&d.bst, bb) != hipSuccess)
         return NRNG_ENOMEM;
-    if (hipMemset(d.status, 0, cap * sizeof(uint64_t)) != hipSuccess)
+    if (hipMemset(d.status, 0, sb) != hipSuccess || hipMemset(d.bst, 0, bb) != hipSuccess)
         return NRNG_EHIP;
     if (hipDeviceSynchronize() != hipSuccess)
         return NRNG_EHIP;
     d.status_cap = cap;
+    d.bcap = bcap;
     return NRNG_OK;
 }
 
@@ -127,15 +140,15 @@ int ensure_streams(DevState &d, uint64_t nstreams, hipStream_t s)
     uint64_t cap = nstreams + nstreams / 4 + 256;
     if (hipDeviceSynchronize() != hipSuccess)
         return NRNG_EHIP;
-    if (d.tile_start)
-        hipFree(d.tile_start);
-    if (d.packed_off)
-        hipFree(d.packed_off);
-    d.tile_start = d.packed_off = nullptr;
+    for (uint64_t **p : {&d.tile_start, &d.block_start, &d.packed_off}) {
+        if (*p)
+            hipFree(*p);
+        *p = nullptr;
+    }
     d.stream_cap = 0;
-    if (hipMalloc(&d.tile_start, (cap + 1) * sizeof(uint64_t)) != hipSuccess)
-        return NRNG_ENOMEM;
-    if (hipMalloc(&d.packed_off, cap * sizeof(uint64_t)) != hipSuccess)
+    if (hipMalloc(&d.tile_start, (cap + 1) * sizeof(uint64_t)) != hipSuccess ||
+        hipMalloc(&d.block_start, (cap + 1) * sizeof(uint64_t)) != hipSuccess ||
+        hipMalloc(&d.packed_off, cap * sizeof(uint64_t)) != hipSuccess)
         return NRNG_ENOMEM;
     d.stream_cap = cap;
     return NRNG_OK;
@@ -179,11 +192,12 @@ uint32_t persistent_grid(DevState &d, int per_cu_occ, uint32_t per_cu_cap, uint6
     return (uint32_t)g;
 }
 
+// Candidates per Polar tile: one wave's 64 lanes times the unroll.
 uint64_t polar_tile_cand(int vi)
 {
     const Variant *v;
     polar_variants(&v);
-    return (uint64_t)v[vi].wg * v[vi].unroll;
+    return 64ull * v[vi].unroll;
 }
 
 // Upper bound on the batched Polar tile count when the valid streams hold
@@ -221,7 +235,7 @@ int polar_common(int mode, uint64_t seed, uint64_t offset, uint64_t *cursor, uin
     uint64_t tiles = force_tiles ? force_tiles : polar_budget_tiles((n + 1) / 2, C);
     if (tiles >= (1ull << 31))
         return NRNG_ERANGE;
-    if ((rc = ensure_status(*d, tiles, s)))
+    if ((rc = ensure_status(*d, tiles, (tiles + 63) / 64, s)))
         return rc;
     PolarArgs a;
     std::memset(&a, 0, sizeof(a));
@@ -236,6 +250,8 @@ int polar_common(int mode, uint64_t seed, uint64_t offset, uint64_t *cursor, uin
     a.consumed = d_consumed;
     a.status = d->status;
     a.status_cap = d->status_cap;
+    a.bst = d->bst;
+    a.bcap = d->bcap;
     a.ctl = d->ctl;
     const uint32_t grid = persistent_grid(*d, polar_blocks_per_cu(*d, mode, dtype, tu.vi), tu.grid_per_cu, tiles);
     return hip_status(launch_polar(mode, dtype, tu.vi, a, grid, s));
@@ -290,11 +306,11 @@ int nrng_reserve(uint64_t max_n, uint32_t max_streams)
     const int nv = polar_variants(&v);
     uint64_t cmin = ~0ull;
     for (int i = 0; i < nv; ++i)
-        cmin = std::min<uint64_t>(cmin, (uint64_t)v[i].wg * v[i].unroll);
+        cmin = std::min<uint64_t>(cmin, 64ull * v[i].unroll);
     uint64_t tiles = polar_budget_tiles((max_n + 1) / 2, cmin);
     if (max_streams)
         tiles = std::max<uint64_t>(tiles, batched_polar_tile_bound(max_n, max_streams, cmin));
-    if ((rc = ensure_status(*d, tiles, nullptr)))
+    if ((rc = ensure_status(*d, tiles, tiles / 64 + max_streams + 1, nullptr)))
         return rc;
     if (max_streams && (rc = ensure_streams(*d, max_streams, nullptr)))
         return rc;
@@ -360,9 +376,8 @@ int nrng_test_polar_budget(uint64_t seed, uint64_t offset, uint64_t n, double mu
                         tiles);
 }
 
-int nrng_batched(int method, uint32_t nstreams, const uint64_t *d_seed, const uint64_t *d_offset,
-                 const uint64_t *d_n, const uint64_t *d_out_off, const double *d_mu, const double *d_sigma,
-                 void *out, uint64_t out_len, int dtype, void *stream, uint64_t *d_consumed)
+int nrng_batched_plan(int method, uint32_t nstreams, const uint64_t *d_n, const uint64_t *d_out_off,
+                      uint64_t out_len, int dtype, void *stream, uint64_t *d_consumed)
 {
     if (!dtype_ok(dtype))
         return NRNG_EDTYPE;
@@ -370,9 +385,7 @@ int nrng_batched(int method, uint32_t nstreams, const uint64_t *d_seed, const ui
         return NRNG_EINVAL;
     if (nstreams == 0)
         return NRNG_OK;
-    if (!d_seed || !d_offset || !d_n || !d_mu || !d_sigma)
-        return NRNG_EINVAL;
-    if (!out && out_len > 0)
+    if (!d_n)
         return NRNG_EINVAL;
     if (out_len > (1ull << 41))
         return NRNG_ERANGE;
@@ -396,14 +409,62 @@ int nrng_batched(int method, uint32_t nstreams, const uint64_t *d_seed, const ui
     p.tile_start = d->tile_start;
     p.packed_off = d->packed_off;
     p.consumed = d_consumed;
-    const uint64_t *off = d_out_off ? d_out_off : d->packed_off;
     if (method == NRNG_METHOD_B1) {
         const Variant *v;
         b1_variants(&v);
         const uint64_t ppl = (dtype == NRNG_F64) ? 1 : (dtype == NRNG_F32 ? 2 : 4);
         p.unit = (uint64_t)v[tu.vi].wg * v[tu.vi].unroll * ppl;
-        if ((rc = hip_status(launch_prep(p, s))))
+    } else {
+        const uint64_t C = polar_tile_cand(tu.vi);
+        const uint64_t bound = batched_polar_tile_bound(out_len, nstreams, C);
+        if (bound == ~0ull)
+            return NRNG_ERANGE;
+        if ((rc = ensure_status(*d, bound, bound / 64 + nstreams + 1, s)))
             return rc;
+        p.unit = C;
+        p.status_cap = d->status_cap;
+        p.block_cap = d->bcap;
+        p.block_start = d->block_start;
+    }
+    if ((rc = hip_status(launch_prep(p, s))))
+        return rc;
+    d->plan_method = method;
+    d->plan_dtype = dtype;
+    d->plan_vi = tu.vi;
+    d->plan_nstreams = nstreams;
+    d->plan_packed = d_out_off == nullptr;
+    return NRNG_OK;
+}
+
+int nrng_batched_exec(int method, uint32_t nstreams, const uint64_t *d_seed, const uint64_t *d_offset,
+                      const uint64_t *d_n, const uint64_t *d_out_off, const double *d_mu, const double *d_sigma,
+                      void *out, int dtype, void *stream, uint64_t *d_consumed)
+{
+    if (!dtype_ok(dtype))
+        return NRNG_EDTYPE;
+    if (method != NRNG_METHOD_B1 && method != NRNG_METHOD_POLAR)
+        return NRNG_EINVAL;
+    if (nstreams == 0)
+        return NRNG_OK;
+    if (!d_seed || !d_offset || !d_n || !d_mu || !d_sigma)
+        return NRNG_EINVAL;
+    hipStream_t s = S(stream);
+    std::lock_guard<std::mutex> lk(g_mu);
+    DevState *d;
+    int rc = get_dev(&d);
+    if (rc)
+        return rc;
+    // the tile table must come from a plan for this method, dtype, variant,
+    // stream count and layout
+    const int kid = method == NRNG_METHOD_B1 ? 2 : 1;
+    const Tune tu = g_tune[kid][dtype];
+    if (d->plan_method != method || d->plan_dtype != dtype || d->plan_vi != tu.vi ||
+        d->plan_nstreams != nstreams || d->plan_packed != (d_out_off == nullptr))
+        return NRNG_EINVAL;
+    if (!out)
+        return NRNG_EINVAL;
+    const uint64_t *off = d_out_off ? d_out_off : d->packed_off;
+    if (method == NRNG_METHOD_B1) {
         B1Args a;
         std::memset(&a, 0, sizeof(a));
         a.out = out;
@@ -418,16 +479,6 @@ int nrng_batched(int method, uint32_t nstreams, const uint64_t *d_seed, const ui
         const uint32_t grid = persistent_grid(*d, b1_blocks_per_cu(*d, 1, dtype, tu.vi), tu.grid_per_cu, 0);
         return hip_status(launch_b1_batched(dtype, tu.vi, a, grid, s));
     }
-    const uint64_t C = polar_tile_cand(tu.vi);
-    const uint64_t bound = batched_polar_tile_bound(out_len, nstreams, C);
-    if (bound == ~0ull)
-        return NRNG_ERANGE;
-    if ((rc = ensure_status(*d, bound, s)))
-        return rc;
-    p.unit = C;
-    p.status_cap = d->status_cap;
-    if ((rc = hip_status(launch_prep(p, s))))
-        return rc;
     PolarArgs a;
     std::memset(&a, 0, sizeof(a));
     a.mu = 0.0;
@@ -442,12 +493,38 @@ int nrng_batched(int method, uint32_t nstreams, const uint64_t *d_seed, const ui
     a.mus = d_mu;
     a.sigmas = d_sigma;
     a.consumed_arr = d_consumed;
+    a.block_start = d->block_start;
     a.status = d->status;
     a.status_cap = d->status_cap;
+    a.bst = d->bst;
+    a.bcap = d->bcap;
     a.ctl = d->ctl;
     const uint32_t grid =
         persistent_grid(*d, polar_blocks_per_cu(*d, MODE_BATCHED, dtype, tu.vi), tu.grid_per_cu, 0);
     return hip_status(launch_polar(MODE_BATCHED, dtype, tu.vi, a, grid, s));
+}
+
+int nrng_batched(int method, uint32_t nstreams, const uint64_t *d_seed, const uint64_t *d_offset,
+                 const uint64_t *d_n, const uint64_t *d_out_off, const double *d_mu, const double *d_sigma,
+                 void *out, uint64_t out_len, int dtype, void *stream, uint64_t *d_consumed)
+{
+    if (!dtype_ok(dtype))
+        return NRNG_EDTYPE;
+    if (method != NRNG_METHOD_B1 && method != NRNG_METHOD_POLAR)
+        return NRNG_EINVAL;
+    if (nstreams == 0)
+        return NRNG_OK;
+    if (!d_seed || !d_offset || !d_n || !d_mu || !d_sigma)
+        return NRNG_EINVAL;
+    if (!out && out_len > 0)
+        return NRNG_EINVAL;
+    int rc = nrng_batched_plan(method, nstreams, d_n, d_out_off, out_len, dtype, stream, d_consumed);
+    if (rc)
+        return rc;
+    if (!out)
+        return NRNG_OK;   // out_len == 0: every stream with n > 0 was skipped by the plan
+    return nrng_batched_exec(method, nstreams, d_seed, d_offset, d_n, d_out_off, d_mu, d_sigma, out, dtype, stream,
+                             d_consumed);
 }
 
 struct FillGraph {
@@ -609,7 +686,7 @@ int nrng_test_polar_xy(const int32_t *d_xy, uint64_t ncand, double mu, double si
     const uint64_t tiles = (ncand + C - 1) / C;
     if (tiles >= (1ull << 31))
         return NRNG_ERANGE;
-    if ((rc = ensure_status(*d, tiles, s)))
+    if ((rc = ensure_status(*d, tiles, (tiles + 63) / 64, s)))
         return rc;
     PolarArgs a;
     std::memset(&a, 0, sizeof(a));
@@ -619,6 +696,8 @@ int nrng_test_polar_xy(const int32_t *d_xy, uint64_t ncand, double mu, double si
     a.out = out;
     a.status = d->status;
     a.status_cap = d->status_cap;
+    a.bst = d->bst;
+    a.bcap = d->bcap;
     a.ctl = d->ctl;
     a.ncand = ncand;
     a.masks = d_mask_words;
@@ -647,7 +726,7 @@ int nrng_polar_trace(uint64_t seed, uint64_t offset, uint64_t ncand, uint64_t *d
     const uint64_t tiles = (ncand + C - 1) / C;
     if (tiles >= (1ull << 31))
         return NRNG_ERANGE;
-    if ((rc = ensure_status(*d, tiles, s)))
+    if ((rc = ensure_status(*d, tiles, (tiles + 63) / 64, s)))
         return rc;
     PolarArgs a;
     std::memset(&a, 0, sizeof(a));
@@ -658,6 +737,8 @@ int nrng_polar_trace(uint64_t seed, uint64_t offset, uint64_t ncand, uint64_t *d
     a.sigma = 1.0;
     a.status = d->status;
     a.status_cap = d->status_cap;
+    a.bst = d->bst;
+    a.bcap = d->bcap;
     a.ctl = d->ctl;
     a.ncand = ncand;
     a.masks = d_mask_words;

@@ -8,6 +8,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "nrng_launch.hpp"
+
 namespace nrng {
 
 // ---------------------------------------------------------------------------
@@ -97,6 +99,23 @@ __device__ __forceinline__ void store_pair(OutT* p, typename out_traits<OutT>::m
     } else {
         store1<OutT>(p, x);
         store1<OutT>(p + 1, y);
+    }
+}
+
+// Store a pair at a pair-aligned p.
+template <typename OutT>
+__device__ __forceinline__ void store_pair_aligned(OutT* p, typename out_traits<OutT>::math x,
+                                                   typename out_traits<OutT>::math y)
+{
+    constexpr int B = out_traits<OutT>::bytes;
+    if constexpr (B == 8) {
+        typedef double d2 __attribute__((ext_vector_type(2)));
+        *reinterpret_cast<d2*>(p) = d2{x, y};
+    } else if constexpr (B == 4) {
+        typedef float f2 __attribute__((ext_vector_type(2)));
+        *reinterpret_cast<f2*>(p) = f2{x, y};
+    } else {
+        *reinterpret_cast<uint32_t*>(p) = (uint32_t)to_bits16<OutT>(x) | ((uint32_t)to_bits16<OutT>(y) << 16);
     }
 }
 
@@ -201,30 +220,68 @@ __device__ __forceinline__ void polar_value_f64(int32_t X, int32_t Y, uint64_t S
 
 // FP32 value.
 //  * ln(s): for s <= 1/2, log2 of sf = S 2^-62 rounded once.  For s > 1/2,
-//    s = 1 - d with d = (2^62 - S) 2^-62 exact; y = 1 - df rounded and the
-//    exact remainder e = (1 - y) - df give ln(s) = ln(y) + e (2 - y), as in
-//    B1 above.  This keeps ln(s) accurate as s -> 1, where ln(s) cancels.
+//    s = 1 - d with d = (2^62 - S) 2^-62 exact; y = 1 - df rounded (also
+//    used as s itself) and the exact remainder e = (1 - y) - df give
+//    ln(s) = ln(y) + e (2 - y), as in B1 above.  This keeps ln(s) accurate
+//    as s -> 1, where ln(s) cancels.
 //  * s < 2^-20 (S < 2^42): ln(s)/s is evaluated in FP64 (exact s; rare).
 //  * r = sqrt(log2(s) * (-2 ln 2 sigma^2) / s); z = r x + mu by an FMA.
+// FP32 radius factor r = sigma sqrt(-2 ln(s) / s) for S >= 2^42.
+__device__ __forceinline__ float polar_r_f32(uint64_t S, float k2)
+{
+    // q = S for s <= 1/2, q = 2^62 - S = d 2^62 (exact) for s > 1/2
+    const bool high = S > (1ull << 61);
+    const uint64_t q = high ? (1ull << 62) - S : S;
+    const float qf = u64_to_f32_scaled(q, 0x1p-30f, 0x1p-62f);
+    const float yv = 1.0f - qf;                            // s, rounded, when high
+    const float e = (1.0f - yv) - qf;
+    const float sf = high ? yv : qf;
+    const float corr = high ? e * (2.0f - yv) : 0.0f;
+    const float l2 = __builtin_fmaf(corr, 1.4426950408889634f, __builtin_amdgcn_logf(sf));
+    return __builtin_amdgcn_sqrtf(l2 * k2 * __builtin_amdgcn_rcpf(sf));
+}
+
+// The same for S < 2^42 (s < 2^-20), evaluated in FP64 with s exact.
+// ln(s) = ln(S) - 62 ln 2; with S = 2^e m, m in [1, 2) (exact), and
+// t = (m - 1) / (m + 1) in [0, 1/3), ln(m) = 2 (t + t^3/3 + t^5/5 + ...),
+// truncated after t^21 (remainder below 2^-40 relative, far below the FP32
+// result's rounding).  The reciprocal and the square root take the hardware
+// FP64 approximations plus Newton steps.  A short routine keeps this rare
+// path light in registers.
+__device__ __forceinline__ double ln_u64_small(uint64_t S)
+{
+    const int e = 63 - __builtin_clzll(S);                 // S >= 1
+    const double m = (double)S * __builtin_ldexp(1.0, -e);  // exact, in [1, 2)
+    const double t = (m - 1.0) / (m + 1.0);
+    const double t2 = t * t;
+    double p = 1.0 / 21;
+    p = p * t2 + 1.0 / 19;
+    p = p * t2 + 1.0 / 17;
+    p = p * t2 + 1.0 / 15;
+    p = p * t2 + 1.0 / 13;
+    p = p * t2 + 1.0 / 11;
+    p = p * t2 + 1.0 / 9;
+    p = p * t2 + 1.0 / 7;
+    p = p * t2 + 1.0 / 5;
+    p = p * t2 + 1.0 / 3;
+    p = p * t2 + 1.0;
+    return 2.0 * t * p + (double)e * 0.69314718055994530942;
+}
+
+__device__ __forceinline__ float polar_r_small(uint64_t S, float sigma)
+{
+    const double s = (double)S * 0x1p-62;                   // exact
+    const double ln_s = ln_u64_small(S) - 62.0 * 0.69314718055994530942;
+    const double q = -2.0 * ln_s / s;
+    return (float)__builtin_sqrt(q) * sigma;
+}
+
+__device__ __forceinline__ bool polar_small(uint64_t S) { return S < (1ull << 42); }
+
 __device__ __forceinline__ void polar_value_f32(int32_t X, int32_t Y, uint64_t S, float mu, float k2,
                                                 float sigma, float& zx, float& zy)
 {
-    float r;
-    if (S < (1ull << 42)) {
-        double s = (double)S * 0x1p-62;                       // exact
-        double rd = sqrt(-2.0 * log(s) / s);
-        r = (float)rd * sigma;
-    } else {
-        const bool high = S > (1ull << 61);
-        const float sf = u64_to_f32_scaled(S, 0x1p-30f, 0x1p-62f);
-        const float df = u64_to_f32_scaled((1ull << 62) - S, 0x1p-30f, 0x1p-62f);
-        const float yv = 1.0f - df;
-        const float e = (1.0f - yv) - df;
-        const float arg = high ? yv : sf;
-        const float corr = high ? e * (2.0f - yv) : 0.0f;
-        const float l2 = __builtin_fmaf(corr, 1.4426950408889634f, __builtin_amdgcn_logf(arg));
-        r = __builtin_amdgcn_sqrtf(l2 * k2 * __builtin_amdgcn_rcpf(sf));
-    }
+    const float r = polar_small(S) ? polar_r_small(S, sigma) : polar_r_f32(S, k2);
     zx = __builtin_fmaf(r, (float)X * 0x1p-31f, mu);
     zy = __builtin_fmaf(r, (float)Y * 0x1p-31f, mu);
 }
@@ -246,6 +303,18 @@ __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v)
     for (int o = 32; o > 0; o >>= 1)
         v += (uint64_t)__shfl_xor((unsigned long long)v, o, 64);
     return v;
+}
+
+// Sum of v over lanes 0 .. k-1 (k wave-uniform, at most 64), read lane by
+// lane into scalar registers; cheaper in registers than a shuffle tree when k
+// is small, which is the common case of the look-back.
+__device__ __forceinline__ uint64_t lane_sum(uint64_t v, int k)
+{
+    const uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+    uint64_t acc = 0;
+    for (int i = 0; i < k; ++i)
+        acc += ((uint64_t)__builtin_amdgcn_readlane(hi, i) << 32) | __builtin_amdgcn_readlane(lo, i);
+    return acc;
 }
 
 __device__ __forceinline__ uint64_t uniform_u64(uint64_t v)
@@ -279,39 +348,136 @@ __device__ __forceinline__ uint64_t st_read(const uint64_t* p)
     return __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Exclusive prefix (accepted pairs before tile lt of a stream whose status
-// words start at st0), by decoupled look-back over windows of 64
-// predecessors read in parallel by one wave.  Predecessor words go from
-// invalid to aggregate to inclusive; the window is summed once every word up
-// to the nearest inclusive one is valid.  Called by all 64 lanes of one wave.
-__device__ __forceinline__ uint64_t lookback(const uint64_t* st0, uint32_t lt, uint32_t tag)
+// One window of a look-back: items i = 0 .. k-1 (k <= 64) are predecessors,
+// nearest first; lane i polls item i through probe(i, valid, inc, val).
+// Items go from invalid to valid, and a valid item is either an aggregate
+// (its own count) or inclusive (the prefix up to and including it).  The
+// window is resolved once every item up to the nearest inclusive one is
+// valid: the result is the sum of their values, and `found` tells whether an
+// inclusive item ended the sum.  An item still missing after spin_limit polls
+// is resolved by help(i), which returns its value and whether it is
+// inclusive -- so the look-back never depends on another wave making
+// progress.  Called by all 64 lanes of a wave; results are wave-uniform.
+struct Resolved {
+    uint64_t val;
+    bool inc;
+};
+
+template <typename Probe, typename Help>
+__device__ __forceinline__ uint64_t window_sum(uint32_t k, uint32_t spin_limit, bool& found, Probe&& probe,
+                                               Help&& help)
 {
     const uint32_t lane = lane_id();
-    uint64_t excl = 0;
-    int64_t pos = (int64_t)lt - 1;
+    const uint64_t kmask = k >= 64 ? ~0ull : ((1ull << k) - 1);
+    uint64_t acc = 0;
+    uint32_t base = 0;     // items below base are already in acc
+    uint32_t spins = 0;
     for (;;) {
-        const int64_t li = pos - (int64_t)lane;
-        bool valid = true, inc = true;
+        bool valid = true, inc = false;
         uint64_t val = 0;
-        if (li >= 0) {
-            const uint64_t w = st_read(st0 + li);
-            valid = (uint32_t)(w >> 42) == tag && ((w >> 40) & 3) != 0;
-            inc = ((w >> 40) & 3) == ST_INC;
-            val = w & ST_VAL_MASK;
-        }
-        const uint64_t vmask = __ballot(valid);
-        const uint64_t imask = __ballot(valid && inc);
+        if (lane >= base && lane < k)
+            probe(lane, valid, inc, val);
+        const uint64_t vmask = __ballot(valid) | ~kmask;
+        const uint64_t imask = __ballot(valid && inc) & kmask;
         const int first = imask ? (int)__builtin_ctzll(imask) : 64;
         const uint64_t need = first >= 63 ? ~0ull : ((2ull << first) - 1);
         if ((vmask & need) == need) {
-            excl += wave_sum_u64((int)lane <= first ? val : 0);
-            if (first < 64)
-                return excl;
-            pos -= 64;
+            acc += lane_sum(val, first < 64 ? first + 1 : (int)k);
+            found = first < 64;
+            return acc;
+        }
+        if (++spins > spin_limit) {
+            // items base .. m-1 are valid aggregates (an inclusive one among
+            // them would have satisfied the test above)
+            const uint32_t m = (uint32_t)__builtin_ctzll(~vmask);
+            acc += lane_sum(val, (int)m);
+            const Resolved r = help(m);
+            acc += r.val;
+            if (r.inc) {
+                found = true;
+                return acc;
+            }
+            base = m + 1;
+            spins = 0;
+            if (base >= k) {
+                found = false;
+                return acc;
+            }
         } else {
             __builtin_amdgcn_s_sleep(1);
         }
     }
+}
+
+// Two-level decoupled look-back for tile lt of a stream (local indices).
+//   st0[t]   tile status words: the tile's count (aggregate), later its
+//            inclusive prefix;
+//   bst0[b]  block status words for blocks of 64 tiles: the block's count
+//            (aggregate), later the inclusive prefix at the block's end.
+// Both kinds are published by the last tile of each block, which reads its
+// 63 block-mates' words (one window) -- no atomic read-modify-write anywhere,
+// so nothing serialises on a shared address.  The exclusive prefix of tile
+// lt comes from at most one window over its own block and, per 64 earlier
+// blocks, one window of block words, independent of how many tiles are in
+// flight.  count_tile(t) recomputes a tile's count when its word is missing
+// for too long; a missing block word is rebuilt from the block's tiles.
+struct LookbackRef {
+    const uint64_t* st0;
+    uint64_t* bst0;
+    uint64_t nts;          // tiles in the stream
+};
+
+template <typename CountTile>
+__device__ __forceinline__ Resolved tiles_window(const LookbackRef& q, uint64_t top, uint32_t k, uint32_t tag,
+                                                 uint32_t spin_limit, CountTile&& count_tile)
+{
+    // tiles top-1, top-2, ..., top-k
+    bool found = false;
+    const uint64_t v = window_sum(
+        k, spin_limit, found,
+        [&](uint32_t i, bool& valid, bool& inc, uint64_t& val) {
+            const uint64_t w = st_read(q.st0 + (top - 1 - i) * kStatusStride);
+            valid = (uint32_t)(w >> 42) == tag && ((w >> 40) & 3) != 0;
+            inc = ((w >> 40) & 3) == ST_INC;
+            val = w & ST_VAL_MASK;
+        },
+        [&](uint32_t i) { return Resolved{count_tile(top - 1 - i), false}; });
+    return Resolved{v, found};
+}
+
+// Level 1 of the look-back: the prefix contributed by blocks b0-1, b0-2, ...
+// (64 block words per window).  Returns the sum up to the nearest inclusive
+// block word (or down to the stream's start).
+template <typename CountTile>
+__device__ __forceinline__ uint64_t lookback_blocks(const LookbackRef& q, uint64_t b0, uint32_t tag,
+                                                    uint32_t spin_limit, CountTile&& count_tile)
+{
+    uint64_t excl = 0;
+    int64_t pos = (int64_t)b0 - 1;
+    while (pos >= 0) {
+        const uint32_t k = pos + 1 >= 64 ? 64u : (uint32_t)(pos + 1);
+        bool found = false;
+        const int64_t top = pos;
+        excl += window_sum(
+            k, spin_limit, found,
+            [&](uint32_t i, bool& valid, bool& inc, uint64_t& val) {
+                const uint64_t w = st_read(q.bst0 + (uint64_t)(top - (int64_t)i) * kStatusStride);
+                valid = (uint32_t)(w >> 42) == tag && ((w >> 40) & 3) != 0;
+                inc = ((w >> 40) & 3) == ST_INC;
+                val = w & ST_VAL_MASK;
+            },
+            [&](uint32_t i) {
+                // rebuild block top - i from its tiles (last tile first)
+                const uint64_t b = (uint64_t)(top - (int64_t)i);
+                const uint64_t end = (b + 1) << 6;
+                const uint64_t e = end < q.nts ? end : q.nts;
+                return tiles_window(q, e, (uint32_t)(e - (b << 6)), tag, spin_limit, count_tile);
+            });
+        if (found)
+            return excl;
+        pos -= k;
+    }
+    return excl;
 }
 
 }  // namespace nrng

@@ -11,7 +11,8 @@ namespace nrng {
 // Compiled launch variants (workgroup size, per-thread unroll).
 // ---------------------------------------------------------------------------
 static const Variant kB1Variants[] = {{256, 1}, {256, 2}, {256, 4}, {512, 2}};
-static const Variant kPolarVariants[] = {{256, 4}, {256, 8}, {512, 4}, {128, 8}};
+// Polar: (workgroup size, candidate slots per lane); a tile is one wave's 64 * unroll candidates
+static const Variant kPolarVariants[] = {{256, 4}, {256, 8}, {256, 16}, {512, 8}};
 constexpr int kNB1 = sizeof(kB1Variants) / sizeof(kB1Variants[0]);
 constexpr int kNPolar = sizeof(kPolarVariants) / sizeof(kPolarVariants[0]);
 
@@ -60,6 +61,25 @@ __device__ __forceinline__ void polar_value(int32_t X, int32_t Y, uint64_t S, co
                                             float &zy)
 {
     polar_value_f32(X, Y, S, cf.mu, cf.k, cf.sigma, zx, zy);
+}
+
+// Split form used by the Polar kernel: the common FP32 path, and the rare
+// FP64 path for s < 2^-20, which runs after the main loop so that its
+// registers do not count against the main loop's.
+__device__ __forceinline__ bool polar_is_rare(uint64_t S, const Coef<double> &) { return false; }
+__device__ __forceinline__ bool polar_is_rare(uint64_t S, const Coef<float> &) { return polar_small(S); }
+
+__device__ __forceinline__ void polar_value_common(int32_t X, int32_t Y, uint64_t S, const Coef<double> &cf,
+                                                   double &zx, double &zy)
+{
+    polar_value_f64(X, Y, S, cf.mu, cf.k, zx, zy);
+}
+__device__ __forceinline__ void polar_value_common(int32_t X, int32_t Y, uint64_t S, const Coef<float> &cf,
+                                                   float &zx, float &zy)
+{
+    const float r = polar_r_f32(S, cf.k);
+    zx = __builtin_fmaf(r, (float)X * 0x1p-31f, cf.mu);
+    zy = __builtin_fmaf(r, (float)Y * 0x1p-31f, cf.mu);
 }
 
 // 16-byte store of 2 * PPL elements (PPL pairs) at a 16-byte aligned p.
@@ -204,35 +224,88 @@ __global__ __launch_bounds__(WG) void b1_batched_kernel(B1Args a)
 }
 
 // ---------------------------------------------------------------------------
-// Polar method.  Candidates are processed in tiles of C = WG * U pairs taken
-// in ticket order; candidate j of a tile lives in wave j / (64 U), unroll
-// slot (j / 64) % U, lane j % 64, so that one ballot per slot is the accept
-// mask of 64 consecutive candidates.  Per tile:
-//   1. hash, exact integer predicate, ballots; per-wave counts to LDS;
-//   2. the tile aggregate is published (inclusive prefix for a stream's first
-//      tile);
-//   3. the deviates of the accepted candidates are computed in registers
-//      (this hides the look-back latency);
-//   4. wave 0 looks back over predecessor status words for the exclusive
-//      prefix and publishes the inclusive one;
-//   5. each accepted candidate stores its pair at output pair index
-//      prefix + (rank within the tile), if that index is below ceil(n/2).
-// A stream's last budget tile continues serially with further candidates
-// if the budget fell short.  The last workgroup to exit resets the control
-// block and, for the device-cursor form, advances the cursor.
+// Polar method.  A tile is one wave's work: C = 64 U candidate pairs;
+// candidate j of a tile lives in unroll slot j / 64 and lane j % 64, so that
+// one ballot per slot is the accept mask of 64 consecutive candidates.  Wave g
+// of the grid (W waves in all) takes tiles g, g + W, g + 2W, ...: there is no
+// global ticket counter (a single-address atomic would serialise the tiles)
+// and no barrier anywhere -- waves only meet through the status words.  Per
+// tile:
+//   1. hash, exact integer predicate, ballots -> the tile's accepted count;
+//   2. the count is published (as the inclusive prefix for a stream's first
+//      tile), the wave looks back over predecessor status words for its
+//      exclusive prefix and publishes the inclusive one;
+//   3. per slot, the accepted lanes compute their deviates and store them at
+//      output pair index prefix + (rank within the tile), if below ceil(n/2).
+// A stream's last budget tile continues serially with further candidates if
+// the budget fell short.  The last wave to exit resets the control block and,
+// for the device-cursor form, advances the cursor.
 // ---------------------------------------------------------------------------
+template <int MODE>
+struct PolarSrc {
+    uint64_t ctr0;
+    const int32_t *xy;
+    uint64_t limit;
+    __device__ __forceinline__ bool pair(uint64_t j, int32_t &X, int32_t &Y) const
+    {
+        if constexpr (MODE == MODE_XY) {
+            const bool inb = j < limit;
+            X = inb ? xy[2 * j] : 0;
+            Y = inb ? xy[2 * j + 1] : 0;
+            return inb;
+        } else {
+            X = (int32_t)splitmix64_hi(ctr0 + 2 * j);
+            Y = (int32_t)splitmix64_hi(ctr0 + 2 * j + 1);
+            return MODE != MODE_TRACE || j < limit;
+        }
+    }
+};
+
+// Accepted count of local tile lt (C candidates), computed by one wave.
+template <int MODE>
+__device__ uint64_t polar_count_tile(const PolarSrc<MODE> &src, uint64_t lt, uint64_t C)
+{
+    const uint32_t lane = lane_id();
+    uint64_t cnt = 0;
+    for (uint64_t b = 0; b < C; b += 64) {
+        int32_t X, Y;
+        const bool inb = src.pair(lt * C + b + lane, X, Y);
+        cnt += (uint64_t)__builtin_popcountll(__ballot(inb && polar_accept(polar_S(X, Y))));
+    }
+    return cnt;
+}
+
+constexpr uint32_t kSpinLimit = 1024;   // polls of a missing status word before computing it
+
+// The per-tile state carried from counting to finishing.
+template <typename OutT, int MODE>
+struct PolarJob {
+    uint64_t t, lt, nts, P, nn, cand0, tcnt;
+    OutT *outp;
+    uint64_t *st0, *bst, *cons;
+    PolarSrc<MODE> src;
+    double mu, sigma;
+    uint64_t l0;        // block-last tiles: prefix within the block (from counting)
+    bool l0_done, l0_inc;
+};
+
 template <typename OutT, int WG, int U, int MODE>
 __global__ __launch_bounds__(WG) void polar_kernel(PolarArgs a)
 {
     using M = typename out_traits<OutT>::math;
+    using Job = PolarJob<OutT, MODE>;
     constexpr int NW = WG / 64;
-    constexpr uint64_t C = (uint64_t)WG * U;
-    __shared__ uint32_t s_cnt[NW];
-    __shared__ uint64_t s_excl;
-    __shared__ uint32_t s_t;
-    __shared__ uint32_t s_wrote, s_last;
+    constexpr uint64_t C = 64ull * U;
 
-    const uint32_t tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    // Each wave parks the candidates of two tiles in its own LDS region: the
+    // tile being finished and the next one being counted.  A lane only ever
+    // reads back what it wrote itself; the ballots are recomputed from the
+    // parked candidates rather than passed between lanes through LDS.
+    __shared__ int2 s_xy[NW][2][U][64];
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t w = threadIdx.x >> 6;
+    const uint64_t gw = (uint64_t)blockIdx.x * NW + w;
+    const uint64_t W = (uint64_t)gridDim.x * NW;
     Ctl *ctl = a.ctl;
     const uint32_t tag = __hip_atomic_load(&ctl->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     uint64_t single_off = a.offset;
@@ -245,133 +318,168 @@ __global__ __launch_bounds__(WG) void polar_kernel(PolarArgs a)
         T = a.tile_start[a.nstreams];
     else
         T = a.ntiles;
-    if (tid == 0)
-        s_wrote = 0;
     bool wrote = false;
 
-    for (;;) {
-        if (tid == 0)
-            s_t = __hip_atomic_fetch_add(&ctl->ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __syncthreads();
-        const uint64_t t = s_t;
-        if (t >= T)
-            break;
-
-        // ---- the job of tile t
-        uint64_t ctr0, P, nn, lt, nts, limit;
-        OutT *outp;
-        uint64_t *st0;
-        uint64_t *cons;
-        double mu_d, sigma_d;
+    auto make_job = [&](uint64_t t) {
+        Job jb;
+        jb.t = t;
+        jb.src.xy = a.xy;
+        jb.src.limit = a.ncand;
+        jb.l0 = 0;
+        jb.l0_done = jb.l0_inc = false;
         if constexpr (MODE == MODE_BATCHED) {
             const uint32_t j = find_stream(a.tile_start, a.nstreams, t);
             const uint64_t ts = a.tile_start[j], te = a.tile_start[j + 1];
-            lt = t - ts;
-            nts = te - ts;
-            nn = a.ns[j];
-            P = (nn + 1) / 2;
-            ctr0 = a.seeds[j] + a.offsets[j];
-            outp = (OutT *)a.out + a.out_off[j];
-            mu_d = a.mus[j];
-            sigma_d = a.sigmas[j];
-            st0 = a.status + ts;
-            cons = a.consumed_arr ? a.consumed_arr + j : nullptr;
-            limit = ~0ull;
+            jb.lt = t - ts;
+            jb.nts = te - ts;
+            jb.nn = a.ns[j];
+            jb.P = (jb.nn + 1) / 2;
+            jb.src.ctr0 = a.seeds[j] + a.offsets[j];
+            jb.outp = (OutT *)a.out + a.out_off[j];
+            jb.mu = a.mus[j];
+            jb.sigma = a.sigmas[j];
+            jb.st0 = a.status + ts * kStatusStride;
+            jb.bst = a.bst + a.block_start[j] * kStatusStride;
+            jb.cons = a.consumed_arr ? a.consumed_arr + j : nullptr;
         } else {
-            lt = t;
-            nts = T;
-            ctr0 = a.seed + single_off;
-            outp = (OutT *)a.out;
-            mu_d = a.mu;
-            sigma_d = a.sigma;
-            st0 = a.status;
+            jb.lt = t;
+            jb.nts = T;
+            jb.src.ctr0 = a.seed + single_off;
+            jb.outp = (OutT *)a.out;
+            jb.mu = a.mu;
+            jb.sigma = a.sigma;
+            jb.st0 = a.status;
+            jb.bst = a.bst;
             if constexpr (MODE == MODE_SINGLE) {
-                nn = a.n;
-                P = (nn + 1) / 2;
-                cons = a.consumed;
-                limit = ~0ull;
+                jb.nn = a.n;
+                jb.P = (jb.nn + 1) / 2;
+                jb.cons = a.consumed;
             } else {
-                nn = ~0ull;
-                P = ~0ull;
-                cons = nullptr;
-                limit = a.ncand;
+                jb.nn = ~0ull;
+                jb.P = ~0ull;
+                jb.cons = nullptr;
             }
         }
-        const Coef<M> cf(mu_d, sigma_d);
-        uint64_t cand0 = lt * C;
-        bool serial = false;
+        jb.cand0 = jb.lt * C;
+        return jb;
+    };
+
+    // 1. hash, exact predicate and ballots of the tile's C candidates,
+    // parked in LDS buffer `buf`; returns the accepted count.
+    auto count_into = [&](const Job &jb, uint64_t cand0, int buf) {
+        uint64_t tcnt = 0;
+#pragma unroll
+        for (int s = 0; s < U; ++s) {
+            const uint64_t j = cand0 + (uint64_t)s * 64 + lane;
+            int32_t X, Y;
+            const bool inb = jb.src.pair(j, X, Y);
+            const uint64_t m = __ballot(inb && polar_accept(polar_S(X, Y)));
+            tcnt += (uint64_t)__builtin_popcountll(m);
+            s_xy[w][buf][s][lane] = make_int2(X, Y);
+        }
+        return tcnt;
+    };
+
+    // Count a tile and publish its aggregate (inclusive for a stream's first
+    // tile).  The last tile of a block also resolves the prefix inside its
+    // block and publishes the block aggregate right away, so that later
+    // blocks never wait on it.
+    auto count = [&](Job &jb, int buf) {
+        jb.tcnt = count_into(jb, jb.cand0, buf);
+        const uint64_t lt = jb.lt;
+        if (lane == 0)
+            st_publish(jb.st0 + lt * kStatusStride, st_pack(tag, lt == 0 ? ST_INC : ST_AGG, jb.tcnt));
+        const bool block_last = (lt & 63) == 63 || lt + 1 == jb.nts;
+        if (block_last && lt != 0) {
+            const LookbackRef q{jb.st0, jb.bst, jb.nts};
+            const uint32_t k0 = (uint32_t)(lt & 63);
+            Resolved r{0, false};
+            if (k0)
+                r = tiles_window(q, lt, k0, tag, kSpinLimit,
+                                 [&](uint64_t t2) { return polar_count_tile<MODE>(jb.src, t2, C); });
+            jb.l0 = r.val;
+            jb.l0_inc = r.inc;
+            jb.l0_done = true;
+            if (!r.inc && lane == 0)
+                st_publish(jb.bst + (lt >> 6) * kStatusStride, st_pack(tag, ST_AGG, r.val + jb.tcnt));
+        }
+    };
+
+    // 2.-3. look back, publish the inclusive prefixes, compute and store the
+    // deviates of tile jb from LDS buffer buf.
+    auto finish = [&](Job &jb, int buf) {
+        const uint64_t lt = jb.lt;
+        const Coef<M> cf(jb.mu, jb.sigma);
+        const bool pair_aligned =
+            (reinterpret_cast<uintptr_t>(jb.outp) & (2 * out_traits<OutT>::bytes - 1)) == 0;
         uint64_t excl = 0;
-
-        for (;;) {
-            // ---- 1. candidates, predicate, ballots
-            int32_t X[U], Y[U];
-            uint64_t S[U], mk[U];
-            uint32_t wcnt = 0;
-#pragma unroll
-            for (int s = 0; s < U; ++s) {
-                const uint64_t j = cand0 + (uint64_t)w * 64 * U + (uint64_t)s * 64 + lane;
-                bool inb = true;
-                if constexpr (MODE == MODE_XY) {
-                    inb = j < limit;
-                    X[s] = inb ? a.xy[2 * j] : 0;
-                    Y[s] = inb ? a.xy[2 * j + 1] : 0;
-                } else {
-                    if constexpr (MODE == MODE_TRACE)
-                        inb = j < limit;
-                    X[s] = (int32_t)splitmix64_hi(ctr0 + 2 * j);
-                    Y[s] = (int32_t)splitmix64_hi(ctr0 + 2 * j + 1);
-                }
-                S[s] = polar_S(X[s], Y[s]);
-                mk[s] = __ballot(inb && polar_accept(S[s]));
-                wcnt += (uint32_t)__builtin_popcountll(mk[s]);
+        if (lt != 0) {
+            const LookbackRef q{jb.st0, jb.bst, jb.nts};
+            auto helper = [&](uint64_t t2) { return polar_count_tile<MODE>(jb.src, t2, C); };
+            Resolved r;
+            if (jb.l0_done) {
+                r = Resolved{jb.l0, jb.l0_inc};
+            } else {
+                const uint32_t k0 = (uint32_t)(lt & 63);
+                r = Resolved{0, false};
+                if (k0)
+                    r = tiles_window(q, lt, k0, tag, kSpinLimit, helper);
             }
+            excl = r.val;
+            if (!r.inc)
+                excl += lookback_blocks(q, lt >> 6, tag, kSpinLimit, helper);
             if (lane == 0)
-                s_cnt[w] = wcnt;
-            __syncthreads();
-            uint32_t tcnt = 0, wpre = 0;
-#pragma unroll
-            for (int k = 0; k < NW; ++k) {
-                const uint32_t c = s_cnt[k];
-                wpre += (k < (int)w) ? c : 0u;
-                tcnt += c;
-            }
-            // ---- 2. publish the aggregate (or the inclusive prefix of tile 0)
-            if (!serial && tid == 0)
-                st_publish(st0 + lt, st_pack(tag, lt == 0 ? ST_INC : ST_AGG, tcnt));
+                st_publish(jb.st0 + lt * kStatusStride, st_pack(tag, ST_INC, excl + jb.tcnt));
+        }
+        if (lane == 0 && ((lt & 63) == 63 || lt + 1 == jb.nts))
+            st_publish(jb.bst + (lt >> 6) * kStatusStride, st_pack(tag, ST_INC, excl + jb.tcnt));
 
-            // ---- 3. values of the accepted candidates
-            M zx[U], zy[U];
-            if constexpr (MODE != MODE_TRACE) {
-#pragma unroll
-                for (int s = 0; s < U; ++s) {
-                    zx[s] = 0;
-                    zy[s] = 0;
-                    if ((mk[s] >> lane) & 1ull)
-                        polar_value(X[s], Y[s], S[s], cf, zx[s], zy[s]);
-                }
-            }
-
-            // ---- 4. look-back
-            if (!serial) {
-                if (w == 0) {
-                    const uint64_t e = lt == 0 ? 0 : lookback(st0, (uint32_t)lt, tag);
-                    if (lane == 0) {
-                        if (lt != 0)
-                            st_publish(st0 + lt, st_pack(tag, ST_INC, e + tcnt));
-                        s_excl = e;
+        const uint64_t P = jb.P, nn = jb.nn;
+        auto store = [&](bool all_in, uint64_t ai, M zx, M zy, uint64_t jj) {
+            OutT *p = jb.outp + 2 * ai;
+            if (all_in) {
+                if (pair_aligned)
+                    store_pair_aligned<OutT>(p, zx, zy);
+                else
+                    store_pair<OutT>(p, zx, zy);
+            } else if (ai < P) {
+                if (2 * ai + 1 < nn)
+                    store_pair<OutT>(p, zx, zy);
+                else
+                    store1<OutT>(p, zx);
+                if constexpr (MODE == MODE_SINGLE || MODE == MODE_BATCHED) {
+                    if (ai == P - 1) {
+                        const uint64_t used = 2 * (jj + 1);
+                        if (jb.cons)
+                            *jb.cons = used;
+                        if constexpr (MODE == MODE_SINGLE) {
+                            __hip_atomic_store(&ctl->consumed, used, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            wrote = true;
+                        }
                     }
                 }
-                __syncthreads();
-                excl = s_excl;
             }
+        };
 
-            // ---- 5. stores
-            uint64_t run = excl + wpre;
+        // the tile itself, from the parked candidates
+        {
+            const uint64_t cand0 = jb.cand0;
+            // fast path: every accepted pair of the tile is needed and complete
+            const bool all_in = excl + jb.tcnt <= P && 2 * (excl + jb.tcnt) <= nn;
+            uint64_t run = excl;
+            uint64_t any_rare = 0;
 #pragma unroll
             for (int s = 0; s < U; ++s) {
-                const uint64_t m = mk[s];
+                const uint64_t jj = cand0 + (uint64_t)s * 64 + lane;
+                const int2 xy = s_xy[w][buf][s][lane];
+                const uint64_t Ss = polar_S(xy.x, xy.y);
+                bool inb = true;
+                if constexpr (MODE == MODE_XY || MODE == MODE_TRACE)
+                    inb = jj < jb.src.limit;
+                const bool acc = inb && polar_accept(Ss);
+                const uint64_t m = __ballot(acc);
                 if constexpr (MODE == MODE_TRACE || MODE == MODE_XY) {
-                    const uint64_t widx = (cand0 + (uint64_t)w * 64 * U + (uint64_t)s * 64) >> 6;
+                    const uint64_t widx = (cand0 + (uint64_t)s * 64) >> 6;
                     if (lane == 0 && widx < (a.ncand + 63) / 64) {
                         a.masks[widx] = m;
                         if (a.word_prefix)
@@ -379,69 +487,113 @@ __global__ __launch_bounds__(WG) void polar_kernel(PolarArgs a)
                     }
                 }
                 if constexpr (MODE != MODE_TRACE) {
-                    if ((m >> lane) & 1ull) {
-                        const uint64_t ai = run + rank_below(m);
-                        if (ai < P) {
-                            OutT *p = outp + 2 * ai;
-                            if (2 * ai + 1 < nn)
-                                store_pair<OutT>(p, zx[s], zy[s]);
-                            else
-                                store1<OutT>(p, zx[s]);
-                            if constexpr (MODE == MODE_SINGLE || MODE == MODE_BATCHED) {
-                                if (ai == P - 1) {
-                                    const uint64_t j = cand0 + (uint64_t)w * 64 * U + (uint64_t)s * 64 + lane;
-                                    const uint64_t used = 2 * (j + 1);
-                                    if (cons)
-                                        *cons = used;
-                                    if constexpr (MODE == MODE_SINGLE) {
-                                        __hip_atomic_store(&ctl->consumed, used, __ATOMIC_RELAXED,
-                                                           __HIP_MEMORY_SCOPE_AGENT);
-                                        wrote = true;
-                                    }
-                                }
-                            }
-                        }
+                    const bool rare = acc && polar_is_rare(Ss, cf);
+                    any_rare |= __ballot(rare);
+                    if (acc && !rare) {
+                        M zx, zy;
+                        polar_value_common(xy.x, xy.y, Ss, cf, zx, zy);
+                        store(all_in, run + rank_below(m), zx, zy, jj);
                     }
                 }
                 run += (uint64_t)__builtin_popcountll(m);
             }
-            const uint64_t incl = excl + tcnt;
-            if constexpr (MODE == MODE_XY) {
-                if (tid == 0 && lt == nts - 1 && a.count_out)
-                    *a.count_out = incl;
+            if constexpr (MODE != MODE_TRACE) {
+                if (any_rare) {   // wave-uniform; about one tile in 2^14
+                    uint64_t run2 = excl;
+#pragma unroll 1
+                    for (int s = 0; s < U; ++s) {
+                        const uint64_t jr = cand0 + (uint64_t)s * 64 + lane;
+                        const int2 xy = s_xy[w][buf][s][lane];
+                        const uint64_t Sr = polar_S(xy.x, xy.y);
+                        bool inb = true;
+                        if constexpr (MODE == MODE_XY)
+                            inb = jr < jb.src.limit;
+                        const uint64_t m = __ballot(inb && polar_accept(Sr));
+                        if (((m >> lane) & 1ull) && polar_is_rare(Sr, cf)) {
+                            M zx, zy;
+                            polar_value(xy.x, xy.y, Sr, cf, zx, zy);
+                            store(all_in, run2 + rank_below(m), zx, zy, jr);
+                        }
+                        run2 += (uint64_t)__builtin_popcountll(m);
+                    }
+                }
             }
-            // ---- continuation past the budget (exact, serial, rare)
-            const bool more = (MODE == MODE_SINGLE || MODE == MODE_BATCHED) && (lt == nts - 1) && incl < P;
-            if (!more)
+        }
+        uint64_t incl = excl + jb.tcnt;
+        if constexpr (MODE == MODE_XY) {
+            if (lane == 0 && lt == jb.nts - 1 && a.count_out)
+                *a.count_out = incl;
+        }
+        // Continuation past the budget (exact, serial, rare): the stream's
+        // last budget tile goes on through further candidates, 64 at a time,
+        // with its prefix already known.
+        if constexpr (MODE == MODE_SINGLE || MODE == MODE_BATCHED) {
+            if (lt == jb.nts - 1) {
+                uint64_t j0 = jb.cand0 + C;
+#pragma unroll 1
+                while (incl < P) {
+                    const uint64_t jj = j0 + lane;
+                    int32_t X, Y;
+                    jb.src.pair(jj, X, Y);
+                    const uint64_t Sc = polar_S(X, Y);
+                    const bool acc = polar_accept(Sc);
+                    const uint64_t m = __ballot(acc);
+                    if (acc) {
+                        M zx, zy;
+                        polar_value(X, Y, Sc, cf, zx, zy);
+                        store(false, incl + rank_below(m), zx, zy, jj);
+                    }
+                    incl += (uint64_t)__builtin_popcountll(m);
+                    j0 += 64;
+                }
+            }
+        }
+    };
+
+    // software pipeline over this wave's tiles g, g + W, ...: the next tile
+    // is counted (and its aggregate published) before the current one looks
+    // back, so the predecessors' words are normally visible by then
+    if (gw < T) {
+        Job cur = make_job(gw);
+        count(cur, 0);
+        int buf = 0;
+        for (;;) {
+            const uint64_t tn = cur.t + W;
+            const bool has_next = tn < T;
+            Job nxt;
+            if (has_next) {
+                nxt = make_job(tn);
+                count(nxt, buf ^ 1);
+            }
+            finish(cur, buf);
+            if (!has_next)
                 break;
-            serial = true;
-            excl = incl;
-            cand0 += C;
-            __syncthreads();   // s_cnt is rewritten by the next pass
+            cur = nxt;
+            buf ^= 1;
         }
     }
 
-    // ---- exit: the last workgroup resets the control block
-    if (wrote)
-        s_wrote = 1;
-    __syncthreads();
-    if (tid == 0) {
+    // ---- exit: the last wave resets the control block
+    const uint64_t wrote_any = __ballot(wrote);
+    if (lane == 0) {
         uint32_t prev;
-        if (s_wrote)
+        if (wrote_any)
             prev = __hip_atomic_fetch_add(&ctl->exited, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         else
             prev = __hip_atomic_fetch_add(&ctl->exited, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        s_last = prev == gridDim.x - 1;
+        wrote = prev == (uint32_t)(W - 1);   // reused: this is the last wave
     }
-    __syncthreads();
-    if (s_last) {
+    const bool last = __ballot(lane == 0 && wrote) != 0;
+    if (last) {
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         const bool wrap = tag + 1 >= kEpochLimit;
         if (wrap) {
-            for (uint64_t i = tid; i < a.status_cap; i += WG)
+            for (uint64_t i = lane; i < a.status_cap * kStatusStride; i += 64)
                 a.status[i] = 0;
+            for (uint64_t i = lane; i < a.bcap * kStatusStride; i += 64)
+                a.bst[i] = 0;
         }
-        if (tid == 0) {
+        if (lane == 0) {
             if constexpr (MODE == MODE_SINGLE) {
                 if (a.cursor) {
                     const uint64_t used = __hip_atomic_load(&ctl->consumed, __ATOMIC_RELAXED,
@@ -450,7 +602,6 @@ __global__ __launch_bounds__(WG) void polar_kernel(PolarArgs a)
                 }
             }
             __hip_atomic_store(&ctl->consumed, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&ctl->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&ctl->exited, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&ctl->epoch, wrap ? 1u : tag + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
@@ -509,19 +660,22 @@ __global__ __launch_bounds__(1024) void prep_kernel(PrepArgs a)
             return (P + a.unit - 1) / a.unit;
         return polar_budget_tiles(P, a.unit);
     };
-    uint64_t tloc = 0, run = nbase;
+    uint64_t tloc = 0, bloc = 0, run = nbase;
     for (uint32_t j = j0; j < j1; ++j) {
         const uint64_t n = a.ns[j];
         const uint64_t off = a.out_off ? a.out_off[j] : run;
         run = sat_add(run, n);
         const bool valid = n <= a.out_len && off <= a.out_len - n;
-        tloc = sat_add(tloc, valid ? tiles_of(n) : 0);
+        const uint64_t tl = valid ? tiles_of(n) : 0;
+        tloc = sat_add(tloc, tl);
+        bloc = sat_add(bloc, (tl + 63) / 64);
     }
-    uint64_t T;
+    uint64_t T, NB;
     const uint64_t tbase = block_exclusive_scan(tloc, sh, T);
-    const bool ok = (a.method == 0 || T <= a.status_cap) && T < (1ull << 40);
+    const uint64_t bbase = block_exclusive_scan(bloc, sh, NB);
+    const bool ok = (a.method == 0 || (T <= a.status_cap && NB <= a.block_cap)) && T < (1ull << 40);
     run = nbase;
-    uint64_t tr = tbase;
+    uint64_t tr = tbase, br = bbase;
     for (uint32_t j = j0; j < j1; ++j) {
         const uint64_t n = a.ns[j];
         const uint64_t off = a.out_off ? a.out_off[j] : run;
@@ -529,7 +683,10 @@ __global__ __launch_bounds__(1024) void prep_kernel(PrepArgs a)
         const bool valid = n <= a.out_len && off <= a.out_len - n;
         const uint64_t tl = (ok && valid) ? tiles_of(n) : 0;
         a.tile_start[j] = ok ? tr : 0;
+        if (a.block_start)
+            a.block_start[j] = ok ? br : 0;
         tr += tl;
+        br += (tl + 63) / 64;
         if (!a.out_off)
             a.packed_off[j] = valid ? off : 0;
         if (a.consumed) {
@@ -543,8 +700,11 @@ __global__ __launch_bounds__(1024) void prep_kernel(PrepArgs a)
             a.consumed[j] = c;
         }
     }
-    if (tid == 0)
+    if (tid == 0) {
         a.tile_start[a.nstreams] = ok ? T : 0;
+        if (a.block_start)
+            a.block_start[a.nstreams] = ok ? NB : 0;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -609,8 +769,8 @@ static const void *polar_fn(int vi)
     switch (vi) {
     case 0: return (const void *)polar_kernel<OutT, 256, 4, MODE>;
     case 1: return (const void *)polar_kernel<OutT, 256, 8, MODE>;
-    case 2: return (const void *)polar_kernel<OutT, 512, 4, MODE>;
-    case 3: return (const void *)polar_kernel<OutT, 128, 8, MODE>;
+    case 2: return (const void *)polar_kernel<OutT, 256, 16, MODE>;
+    case 3: return (const void *)polar_kernel<OutT, 512, 8, MODE>;
     }
     return nullptr;
 }

@@ -8,11 +8,11 @@
 namespace nrng {
 
 // Per-device control block of the look-back kernels.  It resets itself at
-// the end of every launch (the last workgroup to exit clears the ticket and
-// exit counters and advances the epoch), so consecutive launches and graph
-// replays need no memset.
+// the end of every launch (the last workgroup to exit clears the exit
+// counter and advances the epoch), so consecutive launches and graph replays
+// need no memset.
 struct Ctl {
-    uint32_t ticket;     // next tile ticket
+    uint32_t unused;
     uint32_t exited;     // workgroups that have finished
     uint32_t epoch;      // tag of this launch's status words, 1 .. 2^22 - 1
     uint32_t pad;
@@ -20,6 +20,14 @@ struct Ctl {
 };
 
 constexpr uint32_t kEpochLimit = 1u << 22;
+
+// Status words (tile and block) are spaced kStatusStride words apart, so that
+// the words of the tiles in flight at one moment spread over many memory
+// channels instead of sharing a few cache lines.
+#ifndef NRNG_STATUS_STRIDE
+#define NRNG_STATUS_STRIDE 1
+#endif
+constexpr uint64_t kStatusStride = NRNG_STATUS_STRIDE;
 
 enum Mode { MODE_SINGLE = 0, MODE_BATCHED = 1, MODE_TRACE = 2, MODE_XY = 3 };
 
@@ -39,9 +47,12 @@ struct PolarArgs {
     const uint64_t *seeds, *offsets, *ns, *out_off;
     const double *mus, *sigmas;
     uint64_t *consumed_arr;
+    const uint64_t *block_start;  // batched: nstreams + 1 entries, first block of each stream
     // workspace
     uint64_t *status;
     uint64_t status_cap;
+    uint64_t *bst;           // block status words (tagged), bcap entries
+    uint64_t bcap;
     Ctl *ctl;
     // trace / explicit candidates
     uint64_t ncand;
@@ -70,7 +81,9 @@ struct PrepArgs {
     uint64_t out_len;
     uint64_t unit;                   // B1: pairs per tile; Polar: candidates per tile
     uint64_t status_cap;             // Polar: capacity in tiles
+    uint64_t block_cap;              // Polar: capacity in blocks of 64 tiles
     uint64_t *tile_start;            // out: nstreams + 1
+    uint64_t *block_start;           // out (Polar): nstreams + 1
     uint64_t *packed_off;            // out: nstreams (used when out_off is null)
     uint64_t *consumed;              // out (nullable)
 };

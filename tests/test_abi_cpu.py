@@ -93,3 +93,16 @@ def test_tune_table_validation():
 def test_binding_raises_on_error_status():
     with pytest.raises(nb.NrngError):
         nb.nrng_boxmuller(1, 0, 10, 0.0, -1.0, 0x1000, nb.NRNG_F32, 0)
+
+
+def test_binding_checks_tensor_sizes_before_calling():
+    import torch
+    small = torch.empty(10, dtype=torch.float32)
+    with pytest.raises(ValueError):
+        nb.nrng_boxmuller(1, 0, 11, 0.0, 1.0, small, nb.NRNG_F32, 0)
+    with pytest.raises(ValueError):
+        nb.nrng_polar(1, 0, 6, 0.0, 1.0, small, nb.NRNG_F64, 0)
+    with pytest.raises(ValueError):
+        nb.nrng_batched(nb.NRNG_METHOD_POLAR, 2, None, None, None, None, None, None, small, 11, nb.NRNG_F32, 0)
+    with pytest.raises(ValueError):
+        nb.nrng_test_polar_xy(torch.empty(3, dtype=torch.int32), 2, 0.0, 1.0, small, nb.NRNG_F32, None, None, 0)
