@@ -46,8 +46,8 @@
  *   - Return value: NRNG_OK (0) or a negative nrng_status.  Argument errors
  *     are reported before anything is launched and nothing is written.
  *     Nothing prints and nothing aborts.
- *   - The library keeps a small per-device workspace (look-back status words,
- *     tile tables).  Calls that use it (Polar, batched) must be ordered on one
+ *   - The library keeps a per-device workspace (Polar accept masks, about one
+ *     bit per candidate, tile prefix counts, batched tile tables).  Calls that use it (Polar, batched) must be ordered on one
  *     stream per device; concurrent such calls on different streams of one
  *     device race.  The workspace grows on demand, which allocates; during
  *     stream capture growth is refused with NRNG_ECAPTURE, so call
@@ -114,10 +114,14 @@ int nrng_boxmuller(uint64_t seed, uint64_t offset, uint64_t n, double mu, double
  * Algorithm P (Polar method), Section 2, over one stream.
  *   Arguments as nrng_boxmuller.  The acceptance test of step 3 and the
  *   compaction of accepted pairs (the paper's vector gather, Section 2, and
- *   the compress of triples (x_j, y_j, s_j), Section 4) are done in one pass:
- *   wavefront ballots give each accepted candidate its rank in its tile and
- *   tiles find their output offset by decoupled look-back, so accept masks
- *   and output indices are exact integers.
+ *   the compress of triples (x_j, y_j, s_j), Section 4) run as three kernels
+ *   on `stream`: a mask pass (hash, exact test, wavefront ballots -> one
+ *   accept bit per candidate and a count per tile of candidates), a prefix
+ *   scan of the tile counts, and a generate pass in which each lane takes
+ *   consecutive accepted candidates, so accept masks and output indices are
+ *   exact integers and only accepted candidates are transformed.  The
+ *   candidate budget of the mask pass is the expected count plus four
+ *   standard deviations; a stream that needs more continues exactly past it.
  *   d_consumed  optional device pointer (may be NULL): receives the number
  *               of uniforms consumed, 2 (j_last + 1).  Written
  *               asynchronously; no synchronisation.
@@ -128,15 +132,17 @@ int nrng_polar(uint64_t seed, uint64_t offset, uint64_t n, double mu, double sig
 /* Polar method with a device-resident counter offset, for repeated fills
  * captured in a HIP graph: reads the offset from *d_cursor when the kernel
  * runs and advances *d_cursor by the number of uniforms consumed, so that
- * successive calls (or graph replays) continue one stream.  Launches exactly
- * one kernel and allocates nothing once the workspace is reserved
- * (nrng_reserve(n, 0)); NRNG_ECAPTURE otherwise while capturing. */
+ * successive calls (or graph replays) continue one stream.  Launches the
+ * same three kernels as nrng_polar and allocates nothing once the workspace
+ * is reserved (nrng_reserve(n, 0)); NRNG_ECAPTURE otherwise while
+ * capturing. */
 int nrng_polar_dev(uint64_t seed, uint64_t *d_cursor, uint64_t n, double mu, double sigma, void *out,
                    int dtype, void *stream);
 
 /* ------------------------------------------------------------------------
- * Many independent streams in one persistent launch (plus one small set-up
- * kernel that builds the tile table on the device).
+ * Many independent streams in one launch sequence: one small set-up kernel
+ * builds the tile table on the device, then one persistent B1 kernel, or
+ * the three Polar kernels, cover every stream.
  *   method       NRNG_METHOD_B1 or NRNG_METHOD_POLAR
  *   nstreams     number of streams (0 is a no-op)
  *   d_seed[j], d_offset[j], d_n[j]  stream j's seed, first counter, length
@@ -208,10 +214,11 @@ int nrng_tune_variants(int kernel, uint32_t *pairs, int max_pairs);
  * nrng_polar_trace: the accept masks and, per 64-candidate word, the output
  *   pair index of its first candidate (exclusive prefix), for candidates
  *   [0, ncand) of stream (seed, offset), produced by the production Polar
- *   kernel's predicate, ballots and look-back.
- * nrng_test_polar_budget: nrng_polar with the look-back tile budget forced
- *   to `tiles` (>= 1), to exercise the exact continuation path that runs
- *   when a stream needs more candidates than its budget.
+ *   mask pass (predicate and ballots) and prefix scan.
+ * nrng_test_polar_budget: nrng_polar with the candidate budget forced to
+ *   `words` (>= 1) words of 64 candidates, to exercise the exact
+ *   continuation path that runs when a stream needs more candidates than its
+ *   budget.
  * ---------------------------------------------------------------------- */
 int nrng_test_b1_words(const uint64_t *d_words, uint64_t npairs, double mu, double sigma, void *out, int dtype,
                        void *stream);
@@ -220,7 +227,7 @@ int nrng_test_polar_xy(const int32_t *d_xy, uint64_t ncand, double mu, double si
 int nrng_polar_trace(uint64_t seed, uint64_t offset, uint64_t ncand, uint64_t *d_mask_words,
                      uint64_t *d_word_prefix, void *stream);
 int nrng_test_polar_budget(uint64_t seed, uint64_t offset, uint64_t n, double mu, double sigma, void *out,
-                           int dtype, uint32_t tiles, void *stream, uint64_t *d_consumed);
+                           int dtype, uint32_t words, void *stream, uint64_t *d_consumed);
 
 /* ------------------------------------------------------------------------
  * Measurement probes (roofline ceilings and counter calibration).

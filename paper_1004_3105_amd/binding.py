@@ -247,11 +247,11 @@ def nrng_polar_trace(seed, offset, ncand, d_mask_words, d_word_prefix, stream=No
                                                       _ptr(d_mask_words), _ptr(d_word_prefix), _stream(stream)))
 
 
-def nrng_test_polar_budget(seed, offset, n, mu, sigma, out, dtype, tiles, stream=None, d_consumed=None) -> None:
+def nrng_test_polar_budget(seed, offset, n, mu, sigma, out, dtype, words, stream=None, d_consumed=None) -> None:
     _need(out, n * _ESIZE.get(dtype, 0), "nrng_test_polar_budget out")
     _need(d_consumed, 8, "nrng_test_polar_budget d_consumed")
     _check("nrng_test_polar_budget", lib().nrng_test_polar_budget(seed & (2**64 - 1), offset & (2**64 - 1), n, mu,
-                                                                  sigma, _ptr(out), dtype, tiles, _stream(stream),
+                                                                  sigma, _ptr(out), dtype, words, _stream(stream),
                                                                   _ptr(d_consumed)))
 
 

@@ -20,16 +20,21 @@ constexpr int kMaxDev = 64;
 struct DevState {
     bool init = false;
     int cus = 0;
-    Ctl *ctl = nullptr;
-    uint64_t *status = nullptr;
-    uint64_t status_cap = 0;
-    uint64_t *bst = nullptr;        // block status words
-    uint64_t bcap = 0;
+    // Polar workspace (see PolarArgs)
+    uint64_t *masks = nullptr;
+    uint64_t word_cap = 0;
+    uint32_t *ipfx = nullptr;
+    uint64_t tile_cap = 0;
+    uint32_t *csum = nullptr;
+    uint64_t *cpfx = nullptr;
+    uint64_t *misc = nullptr;
+    // batched tables
     uint64_t *tile_start = nullptr;
-    uint64_t *block_start = nullptr;
+    uint64_t *stream_words = nullptr;
     uint64_t *packed_off = nullptr;
     uint64_t stream_cap = 0;
-    int occ_polar[4][4][8] = {};     // [mode][dtype][variant], 0 = not queried
+    int occ_polar[4][4][8] = {};     // generate kernel: [mode][dtype][variant], 0 = not queried
+    int occ_mask[4][8] = {};         // mask kernel: [mode][variant]
     int occ_b1[2][4][8] = {};        // [batched][dtype][variant]
     // the tile table currently in the workspace (from nrng_batched_plan)
     int plan_method = -1, plan_dtype = -1, plan_vi = -1;
@@ -88,46 +93,45 @@ int get_dev(DevState **out)
         if (hipGetDeviceProperties(&prop, dev) != hipSuccess)
             return NRNG_ENODEV;
         d.cus = prop.multiProcessorCount;
-        if (hipMalloc(&d.ctl, sizeof(Ctl)) != hipSuccess)
+        if (hipMalloc(&d.misc, 8 * sizeof(uint64_t)) != hipSuccess)
             return NRNG_ENOMEM;
-        Ctl c0 = {0, 0, 1, 0, 0};
-        if (hipMemcpy(d.ctl, &c0, sizeof(Ctl), hipMemcpyHostToDevice) != hipSuccess)
-            return NRNG_EHIP;
         d.init = true;
     }
     *out = &d;
     return NRNG_OK;
 }
 
-// Grow the look-back arrays to at least `tiles` tile words and `blocks`
-// block words (all zeroed).
-int ensure_status(DevState &d, uint64_t tiles, uint64_t blocks, hipStream_t s)
+// Grow the Polar workspace to at least `tiles` tiles and `words` mask words.
+// Nothing in it needs clearing: every kernel writes what the next one reads.
+int ensure_polar_ws(DevState &d, uint64_t tiles, uint64_t words, hipStream_t s)
 {
-    if (tiles <= d.status_cap && blocks <= d.bcap)
+    if (tiles <= d.tile_cap && words <= d.word_cap)
         return NRNG_OK;
     if (capturing(s))
         return NRNG_ECAPTURE;
-    if (tiles > (1ull << 36) || blocks > (1ull << 36))
+    if (tiles > (1ull << 36) || words > (1ull << 40))
         return NRNG_ERANGE;
-    const uint64_t cap = std::max<uint64_t>(tiles + tiles / 4 + 1024, d.status_cap);
-    const uint64_t bcap = std::max<uint64_t>(blocks + blocks / 4 + 256, d.bcap);
+    const uint64_t tcap = std::max<uint64_t>(tiles + tiles / 4 + 1024, d.tile_cap);
+    const uint64_t wcap = std::max<uint64_t>(words + words / 4 + 4096, d.word_cap);
+    const uint64_t chunks = tcap / kChunkTiles + 2;
     if (hipDeviceSynchronize() != hipSuccess)
         return NRNG_EHIP;
-    for (uint64_t **p : {&d.status, &d.bst}) {
-        if (*p)
-            hipFree(*p);
-        *p = nullptr;
-    }
-    d.status_cap = d.bcap = 0;
-    const size_t sb = cap * kStatusStride * sizeof(uint64_t), bb = bcap * kStatusStride * sizeof(uint64_t);
-    if (hipMalloc(&d.status, sb) != hipSuccess || hipMalloc(&d.bst, bb) != hipSuccess)
+    hipFree(d.masks);
+    hipFree(d.ipfx);
+    hipFree(d.csum);
+    hipFree(d.cpfx);
+    d.masks = nullptr;
+    d.ipfx = nullptr;
+    d.csum = nullptr;
+    d.cpfx = nullptr;
+    d.tile_cap = d.word_cap = 0;
+    if (hipMalloc(&d.masks, wcap * sizeof(uint64_t)) != hipSuccess ||
+        hipMalloc(&d.ipfx, tcap * sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc(&d.csum, chunks * sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc(&d.cpfx, (chunks + 1) * sizeof(uint64_t)) != hipSuccess)
         return NRNG_ENOMEM;
-    if (hipMemset(d.status, 0, sb) != hipSuccess || hipMemset(d.bst, 0, bb) != hipSuccess)
-        return NRNG_EHIP;
-    if (hipDeviceSynchronize() != hipSuccess)
-        return NRNG_EHIP;
-    d.status_cap = cap;
-    d.bcap = bcap;
+    d.tile_cap = tcap;
+    d.word_cap = wcap;
     return NRNG_OK;
 }
 
@@ -140,14 +144,14 @@ int ensure_streams(DevState &d, uint64_t nstreams, hipStream_t s)
     uint64_t cap = nstreams + nstreams / 4 + 256;
     if (hipDeviceSynchronize() != hipSuccess)
         return NRNG_EHIP;
-    for (uint64_t **p : {&d.tile_start, &d.block_start, &d.packed_off}) {
+    for (uint64_t **p : {&d.tile_start, &d.stream_words, &d.packed_off}) {
         if (*p)
             hipFree(*p);
         *p = nullptr;
     }
     d.stream_cap = 0;
     if (hipMalloc(&d.tile_start, (cap + 1) * sizeof(uint64_t)) != hipSuccess ||
-        hipMalloc(&d.block_start, (cap + 1) * sizeof(uint64_t)) != hipSuccess ||
+        hipMalloc(&d.stream_words, (cap + 1) * sizeof(uint64_t)) != hipSuccess ||
         hipMalloc(&d.packed_off, cap * sizeof(uint64_t)) != hipSuccess)
         return NRNG_ENOMEM;
     d.stream_cap = cap;
@@ -160,6 +164,18 @@ int polar_blocks_per_cu(DevState &d, int mode, int dtype, int vi)
     if (o == 0) {
         int b = 0;
         if (occupancy_polar(mode, dtype, vi, &b) != (int)hipSuccess || b <= 0)
+            b = 1;
+        o = b;
+    }
+    return o;
+}
+
+int polar_mask_blocks_per_cu(DevState &d, int mode, int vi)
+{
+    int &o = d.occ_mask[mode][vi];
+    if (o == 0) {
+        int b = 0;
+        if (occupancy_polar_mask(mode, vi, &b) != (int)hipSuccess || b <= 0)
             b = 1;
         o = b;
     }
@@ -192,28 +208,57 @@ uint32_t persistent_grid(DevState &d, int per_cu_occ, uint32_t per_cu_cap, uint6
     return (uint32_t)g;
 }
 
-// Candidates per Polar tile: one wave's 64 lanes times the unroll.
-uint64_t polar_tile_cand(int vi)
+// Mask words per Polar tile and waves per generate workgroup.
+uint64_t polar_tile_words(int vi)
 {
     const Variant *v;
     polar_variants(&v);
-    return 64ull * v[vi].unroll;
+    return v[vi].unroll;
 }
 
-// Upper bound on the batched Polar tile count when the valid streams hold
-// at most out_len normals: each stream of P >= 1 pairs has at most
-// (3.6346 P + 64) / C + 1 tiles (see polar_budget_tiles).
-uint64_t batched_polar_tile_bound(uint64_t out_len, uint64_t nstreams, uint64_t C)
+uint64_t polar_gen_waves(int vi)
+{
+    const Variant *v;
+    polar_variants(&v);
+    return v[vi].wg / 64;
+}
+
+// Upper bound on the total candidate budget, in words, of a batch whose valid
+// streams hold at most out_len normals: each stream of P >= 1 pairs has a
+// budget of at most (3.6346 P + 64) / 64 + 1 words (see polar_budget_words).
+uint64_t batched_polar_word_bound(uint64_t out_len, uint64_t nstreams)
 {
     const double pairs = ((double)out_len + (double)nstreams) / 2.0;
-    const double b = (3.6346 * pairs + 64.0 * (double)nstreams) / (double)C + (double)nstreams + 2.0;
+    const double b = (3.6346 * pairs + 64.0 * (double)nstreams) / 64.0 + (double)nstreams + 2.0;
     if (b > 1.0e15)
         return ~0ull;
     return (uint64_t)b;
 }
 
-int polar_common(int mode, uint64_t seed, uint64_t offset, uint64_t *cursor, uint64_t n, double mu, double sigma,
-                 void *out, int dtype, hipStream_t s, uint64_t *d_consumed, uint32_t force_tiles)
+// Workspace needed by a batch with tiles of U words: tiles <= words / U + N + 1
+// and tiles * U <= words + (N + 1) U.
+void batched_polar_need(uint64_t word_bound, uint64_t nstreams, uint64_t U, uint64_t *tiles, uint64_t *words)
+{
+    *tiles = word_bound / U + nstreams + 1;
+    *words = word_bound + (nstreams + 1) * U;
+}
+
+PolarArgs polar_args(DevState &d)
+{
+    PolarArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.masks = d.masks;
+    a.ipfx = d.ipfx;
+    a.csum = d.csum;
+    a.cpfx = d.cpfx;
+    a.misc = d.misc;
+    return a;
+}
+
+// Single-stream Polar (also the device-cursor form): `words` is the
+// candidate budget, normally polar_budget_words of the pair count.
+int polar_common(uint64_t seed, uint64_t offset, uint64_t *cursor, uint64_t n, double mu, double sigma, void *out,
+                 int dtype, hipStream_t s, uint64_t *d_consumed, uint64_t force_words)
 {
     if (!dtype_ok(dtype))
         return NRNG_EDTYPE;
@@ -231,30 +276,65 @@ int polar_common(int mode, uint64_t seed, uint64_t offset, uint64_t *cursor, uin
     if ((rc = get_dev(&d)))
         return rc;
     const Tune tu = g_tune[1][dtype];
-    const uint64_t C = polar_tile_cand(tu.vi);
-    uint64_t tiles = force_tiles ? force_tiles : polar_budget_tiles((n + 1) / 2, C);
-    if (tiles >= (1ull << 31))
-        return NRNG_ERANGE;
-    if ((rc = ensure_status(*d, tiles, (tiles + 63) / 64, s)))
+    const uint64_t U = polar_tile_words(tu.vi);
+    const uint64_t words = force_words ? force_words : polar_budget_words((n + 1) / 2);
+    const uint64_t tiles = (words + U - 1) / U;
+    if ((rc = ensure_polar_ws(*d, tiles, tiles * U, s)))
         return rc;
-    PolarArgs a;
-    std::memset(&a, 0, sizeof(a));
+    PolarArgs a = polar_args(*d);
     a.seed = seed;
     a.offset = offset;
     a.cursor = cursor;
     a.n = n;
-    a.ntiles = (uint32_t)tiles;
+    a.nwords = words;
+    a.ntiles = tiles;
     a.mu = mu;
     a.sigma = sigma;
     a.out = out;
     a.consumed = d_consumed;
-    a.status = d->status;
-    a.status_cap = d->status_cap;
-    a.bst = d->bst;
-    a.bcap = d->bcap;
-    a.ctl = d->ctl;
-    const uint32_t grid = persistent_grid(*d, polar_blocks_per_cu(*d, mode, dtype, tu.vi), tu.grid_per_cu, tiles);
-    return hip_status(launch_polar(mode, dtype, tu.vi, a, grid, s));
+    const uint64_t chunks = (tiles + kChunkTiles - 1) / kChunkTiles;
+    const uint32_t gm = persistent_grid(*d, polar_mask_blocks_per_cu(*d, MODE_SINGLE, tu.vi), 0, chunks);
+    const uint64_t nw = polar_gen_waves(tu.vi);
+    const uint32_t gg = persistent_grid(*d, polar_blocks_per_cu(*d, MODE_SINGLE, dtype, tu.vi), tu.grid_per_cu,
+                                        (tiles + nw - 1) / nw);
+    return hip_status(launch_polar(MODE_SINGLE, dtype, tu.vi, a, gm, gg, s));
+}
+
+// Trace and explicit-candidate hooks: masks go to the caller's buffer.
+int polar_hook(int mode, uint64_t seed, uint64_t offset, uint64_t ncand, const int32_t *xy, double mu,
+               double sigma, void *out, int dtype, uint64_t *masks, uint64_t *word_prefix, uint64_t *count,
+               hipStream_t s)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    DevState *d;
+    int rc = get_dev(&d);
+    if (rc)
+        return rc;
+    const Tune tu = g_tune[1][dtype];
+    const uint64_t U = polar_tile_words(tu.vi);
+    const uint64_t words = (ncand + 63) / 64;
+    const uint64_t tiles = (words + U - 1) / U;
+    if ((rc = ensure_polar_ws(*d, tiles, 0, s)))
+        return rc;
+    PolarArgs a = polar_args(*d);
+    a.seed = seed;
+    a.offset = offset;
+    a.nwords = words;
+    a.ntiles = tiles;
+    a.mu = mu;
+    a.sigma = sigma;
+    a.out = out;
+    a.ncand = ncand;
+    a.masks = masks;
+    a.word_prefix = word_prefix;
+    a.xy = xy;
+    a.count_out = count;
+    const uint64_t chunks = (tiles + kChunkTiles - 1) / kChunkTiles;
+    const uint32_t gm = persistent_grid(*d, polar_mask_blocks_per_cu(*d, mode, tu.vi), 0, chunks);
+    const uint64_t nw = polar_gen_waves(tu.vi);
+    const uint32_t gg =
+        persistent_grid(*d, polar_blocks_per_cu(*d, mode, dtype, tu.vi), tu.grid_per_cu, (tiles + nw - 1) / nw);
+    return hip_status(launch_polar(mode, dtype, tu.vi, a, gm, gg, s));
 }
 
 }  // namespace
@@ -276,7 +356,7 @@ const char *nrng_strerror(int status)
     return "unknown status";
 }
 
-int nrng_version(void) { return 10000; }
+int nrng_version(void) { return 10100; }
 
 int nrng_init(void)
 {
@@ -301,16 +381,26 @@ int nrng_reserve(uint64_t max_n, uint32_t max_streams)
     int rc = get_dev(&d);
     if (rc)
         return rc;
-    // the smallest tile of any variant gives the largest tile count
     const Variant *v;
     const int nv = polar_variants(&v);
-    uint64_t cmin = ~0ull;
-    for (int i = 0; i < nv; ++i)
-        cmin = std::min<uint64_t>(cmin, 64ull * v[i].unroll);
-    uint64_t tiles = polar_budget_tiles((max_n + 1) / 2, cmin);
-    if (max_streams)
-        tiles = std::max<uint64_t>(tiles, batched_polar_tile_bound(max_n, max_streams, cmin));
-    if ((rc = ensure_status(*d, tiles, tiles / 64 + max_streams + 1, nullptr)))
+    const uint64_t sw = polar_budget_words((max_n + 1) / 2);
+    const uint64_t wb = max_streams ? batched_polar_word_bound(max_n, max_streams) : 0;
+    if (wb == ~0ull)
+        return NRNG_ERANGE;
+    uint64_t tiles = 0, words = 0;
+    for (int i = 0; i < nv; ++i) {
+        const uint64_t U = v[i].unroll;
+        const uint64_t t1 = (sw + U - 1) / U;
+        tiles = std::max(tiles, t1);
+        words = std::max(words, t1 * U);
+        if (max_streams) {
+            uint64_t t2, w2;
+            batched_polar_need(wb, max_streams, U, &t2, &w2);
+            tiles = std::max(tiles, t2);
+            words = std::max(words, w2);
+        }
+    }
+    if ((rc = ensure_polar_ws(*d, tiles, words, nullptr)))
         return rc;
     if (max_streams && (rc = ensure_streams(*d, max_streams, nullptr)))
         return rc;
@@ -356,7 +446,7 @@ int nrng_boxmuller(uint64_t seed, uint64_t offset, uint64_t n, double mu, double
 int nrng_polar(uint64_t seed, uint64_t offset, uint64_t n, double mu, double sigma, void *out, int dtype,
                void *stream, uint64_t *d_consumed)
 {
-    return polar_common(MODE_SINGLE, seed, offset, nullptr, n, mu, sigma, out, dtype, S(stream), d_consumed, 0);
+    return polar_common(seed, offset, nullptr, n, mu, sigma, out, dtype, S(stream), d_consumed, 0);
 }
 
 int nrng_polar_dev(uint64_t seed, uint64_t *d_cursor, uint64_t n, double mu, double sigma, void *out, int dtype,
@@ -364,16 +454,15 @@ int nrng_polar_dev(uint64_t seed, uint64_t *d_cursor, uint64_t n, double mu, dou
 {
     if (!d_cursor)
         return NRNG_EINVAL;
-    return polar_common(MODE_SINGLE, seed, 0, d_cursor, n, mu, sigma, out, dtype, S(stream), nullptr, 0);
+    return polar_common(seed, 0, d_cursor, n, mu, sigma, out, dtype, S(stream), nullptr, 0);
 }
 
 int nrng_test_polar_budget(uint64_t seed, uint64_t offset, uint64_t n, double mu, double sigma, void *out,
-                           int dtype, uint32_t tiles, void *stream, uint64_t *d_consumed)
+                           int dtype, uint32_t words, void *stream, uint64_t *d_consumed)
 {
-    if (tiles == 0)
+    if (words == 0)
         return NRNG_EINVAL;
-    return polar_common(MODE_SINGLE, seed, offset, nullptr, n, mu, sigma, out, dtype, S(stream), d_consumed,
-                        tiles);
+    return polar_common(seed, offset, nullptr, n, mu, sigma, out, dtype, S(stream), d_consumed, words);
 }
 
 int nrng_batched_plan(int method, uint32_t nstreams, const uint64_t *d_n, const uint64_t *d_out_off,
@@ -415,16 +504,18 @@ int nrng_batched_plan(int method, uint32_t nstreams, const uint64_t *d_n, const 
         const uint64_t ppl = (dtype == NRNG_F64) ? 1 : (dtype == NRNG_F32 ? 2 : 4);
         p.unit = (uint64_t)v[tu.vi].wg * v[tu.vi].unroll * ppl;
     } else {
-        const uint64_t C = polar_tile_cand(tu.vi);
-        const uint64_t bound = batched_polar_tile_bound(out_len, nstreams, C);
-        if (bound == ~0ull)
+        const uint64_t U = polar_tile_words(tu.vi);
+        const uint64_t wb = batched_polar_word_bound(out_len, nstreams);
+        if (wb == ~0ull)
             return NRNG_ERANGE;
-        if ((rc = ensure_status(*d, bound, bound / 64 + nstreams + 1, s)))
+        uint64_t tiles, words;
+        batched_polar_need(wb, nstreams, U, &tiles, &words);
+        if ((rc = ensure_polar_ws(*d, tiles, words, s)))
             return rc;
-        p.unit = C;
-        p.status_cap = d->status_cap;
-        p.block_cap = d->bcap;
-        p.block_start = d->block_start;
+        p.unit = U;
+        p.word_cap = d->word_cap;
+        p.tile_cap = d->tile_cap;
+        p.stream_words = d->stream_words;
     }
     if ((rc = hip_status(launch_prep(p, s))))
         return rc;
@@ -479,13 +570,13 @@ int nrng_batched_exec(int method, uint32_t nstreams, const uint64_t *d_seed, con
         const uint32_t grid = persistent_grid(*d, b1_blocks_per_cu(*d, 1, dtype, tu.vi), tu.grid_per_cu, 0);
         return hip_status(launch_b1_batched(dtype, tu.vi, a, grid, s));
     }
-    PolarArgs a;
-    std::memset(&a, 0, sizeof(a));
+    PolarArgs a = polar_args(*d);
     a.mu = 0.0;
     a.sigma = 1.0;
     a.out = out;
     a.nstreams = nstreams;
     a.tile_start = d->tile_start;
+    a.stream_words = d->stream_words;
     a.seeds = d_seed;
     a.offsets = d_offset;
     a.ns = d_n;
@@ -493,15 +584,10 @@ int nrng_batched_exec(int method, uint32_t nstreams, const uint64_t *d_seed, con
     a.mus = d_mu;
     a.sigmas = d_sigma;
     a.consumed_arr = d_consumed;
-    a.block_start = d->block_start;
-    a.status = d->status;
-    a.status_cap = d->status_cap;
-    a.bst = d->bst;
-    a.bcap = d->bcap;
-    a.ctl = d->ctl;
-    const uint32_t grid =
+    const uint32_t gm = persistent_grid(*d, polar_mask_blocks_per_cu(*d, MODE_BATCHED, tu.vi), 0, 0);
+    const uint32_t gg =
         persistent_grid(*d, polar_blocks_per_cu(*d, MODE_BATCHED, dtype, tu.vi), tu.grid_per_cu, 0);
-    return hip_status(launch_polar(MODE_BATCHED, dtype, tu.vi, a, grid, s));
+    return hip_status(launch_polar(MODE_BATCHED, dtype, tu.vi, a, gm, gg, s));
 }
 
 int nrng_batched(int method, uint32_t nstreams, const uint64_t *d_seed, const uint64_t *d_offset,
@@ -676,36 +762,8 @@ int nrng_test_polar_xy(const int32_t *d_xy, uint64_t ncand, double mu, double si
         return NRNG_OK;
     if (!d_xy || !out || !d_mask_words || !d_count)
         return NRNG_EINVAL;
-    hipStream_t s = S(stream);
-    std::lock_guard<std::mutex> lk(g_mu);
-    DevState *d;
-    if ((rc = get_dev(&d)))
-        return rc;
-    const Tune tu = g_tune[1][dtype];
-    const uint64_t C = polar_tile_cand(tu.vi);
-    const uint64_t tiles = (ncand + C - 1) / C;
-    if (tiles >= (1ull << 31))
-        return NRNG_ERANGE;
-    if ((rc = ensure_status(*d, tiles, (tiles + 63) / 64, s)))
-        return rc;
-    PolarArgs a;
-    std::memset(&a, 0, sizeof(a));
-    a.ntiles = (uint32_t)tiles;
-    a.mu = mu;
-    a.sigma = sigma;
-    a.out = out;
-    a.status = d->status;
-    a.status_cap = d->status_cap;
-    a.bst = d->bst;
-    a.bcap = d->bcap;
-    a.ctl = d->ctl;
-    a.ncand = ncand;
-    a.masks = d_mask_words;
-    a.word_prefix = nullptr;
-    a.xy = d_xy;
-    a.count_out = d_count;
-    const uint32_t grid = persistent_grid(*d, polar_blocks_per_cu(*d, MODE_XY, dtype, tu.vi), tu.grid_per_cu, tiles);
-    return hip_status(launch_polar(MODE_XY, dtype, tu.vi, a, grid, s));
+    return polar_hook(MODE_XY, 0, 0, ncand, d_xy, mu, sigma, out, dtype, d_mask_words, nullptr, d_count,
+                      S(stream));
 }
 
 int nrng_polar_trace(uint64_t seed, uint64_t offset, uint64_t ncand, uint64_t *d_mask_words,
@@ -715,37 +773,8 @@ int nrng_polar_trace(uint64_t seed, uint64_t offset, uint64_t ncand, uint64_t *d
         return NRNG_OK;
     if (!d_mask_words || !d_word_prefix)
         return NRNG_EINVAL;
-    hipStream_t s = S(stream);
-    std::lock_guard<std::mutex> lk(g_mu);
-    DevState *d;
-    int rc = get_dev(&d);
-    if (rc)
-        return rc;
-    const Tune tu = g_tune[1][NRNG_F32];
-    const uint64_t C = polar_tile_cand(tu.vi);
-    const uint64_t tiles = (ncand + C - 1) / C;
-    if (tiles >= (1ull << 31))
-        return NRNG_ERANGE;
-    if ((rc = ensure_status(*d, tiles, (tiles + 63) / 64, s)))
-        return rc;
-    PolarArgs a;
-    std::memset(&a, 0, sizeof(a));
-    a.seed = seed;
-    a.offset = offset;
-    a.ntiles = (uint32_t)tiles;
-    a.mu = 0.0;
-    a.sigma = 1.0;
-    a.status = d->status;
-    a.status_cap = d->status_cap;
-    a.bst = d->bst;
-    a.bcap = d->bcap;
-    a.ctl = d->ctl;
-    a.ncand = ncand;
-    a.masks = d_mask_words;
-    a.word_prefix = d_word_prefix;
-    const uint32_t grid =
-        persistent_grid(*d, polar_blocks_per_cu(*d, MODE_TRACE, NRNG_F32, tu.vi), tu.grid_per_cu, tiles);
-    return hip_status(launch_polar(MODE_TRACE, NRNG_F32, tu.vi, a, grid, s));
+    return polar_hook(MODE_TRACE, seed, offset, ncand, nullptr, 0.0, 1.0, nullptr, NRNG_F32, d_mask_words,
+                      d_word_prefix, nullptr, S(stream));
 }
 
 int nrng_probe_store(void *out, uint64_t nbytes, void *stream)

@@ -27,16 +27,20 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t c)
     return z ^ (z >> 31);
 }
 
-// Top 32 bits of the hash only: the low half of the last product and of the
-// final xor-shift are never formed.
-__device__ __forceinline__ uint32_t splitmix64_hi(uint64_t c)
+constexpr uint64_t kGamma = 0x9E3779B97F4A7C15ull;
+
+// Top 32 bits of the hash of counter c, given z = c + kGamma: the low half
+// of the last product and of the final xor-shift are never formed.  Loops
+// over consecutive counters keep z itself and step it.
+__device__ __forceinline__ uint32_t splitmix64_mix_hi(uint64_t z)
 {
-    uint64_t z = c + 0x9E3779B97F4A7C15ull;
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
     uint32_t h = (uint32_t)(z >> 32);
     return h ^ (h >> 31);
 }
+
+__device__ __forceinline__ uint32_t splitmix64_hi(uint64_t c) { return splitmix64_mix_hi(c + kGamma); }
 
 // ---------------------------------------------------------------------------
 // Output element types.  OutT is the storage type; the arithmetic is FP64 for
@@ -123,10 +127,20 @@ __device__ __forceinline__ void store_pair_aligned(OutT* p, typename out_traits<
 // Conversions of 64-bit integers to float with relative error below 2^-23
 // (the high word is converted and scaled, the low word added by an FMA).
 // ---------------------------------------------------------------------------
+// One v_cvt_f32_u32.  Written as an instruction because the compiler
+// otherwise recognises (float)(uint32_t)(q >> 32) as a 64-bit conversion and
+// expands it into a normalising shift sequence.
+__device__ __forceinline__ float cvt_f32_u32(uint32_t x)
+{
+    float r;
+    asm("v_cvt_f32_u32 %0, %1" : "=v"(r) : "v"(x));
+    return r;
+}
+
 __device__ __forceinline__ float u64_to_f32_scaled(uint64_t q, float scale_hi, float scale_lo)
 {
-    float hi = (float)(uint32_t)(q >> 32);
-    float lo = (float)(uint32_t)q;
+    const float hi = cvt_f32_u32((uint32_t)(q >> 32));
+    const float lo = (float)(uint32_t)q;
     return __builtin_fmaf(hi, scale_hi, lo * scale_lo);
 }
 
@@ -196,16 +210,17 @@ __device__ __forceinline__ void b1_pair_f32(uint64_t ku, uint32_t kv_hi, float m
 // x = X 2^-31, y = Y 2^-31, s = S 2^-62 with S = X^2 + Y^2 in uint64.
 // Accept iff 0 < S < 2^62 (s < 1 decided exactly; s = 0 rejected).
 // ---------------------------------------------------------------------------
+// X^2 and Y^2 are at most 2^62, so the sum is exact in uint64 (two signed
+// 32 x 32 -> 64-bit multiply-adds).
 __device__ __forceinline__ uint64_t polar_S(int32_t X, int32_t Y)
 {
-    uint32_t ax = (uint32_t)(X < 0 ? -(int64_t)X : (int64_t)X);
-    uint32_t ay = (uint32_t)(Y < 0 ? -(int64_t)Y : (int64_t)Y);
-    return (uint64_t)ax * ax + (uint64_t)ay * ay;
+    return (uint64_t)((int64_t)X * (int64_t)X) + (uint64_t)((int64_t)Y * (int64_t)Y);
 }
 
+// 0 < S < 2^62 as one unsigned comparison of S - 1.
 __device__ __forceinline__ bool polar_accept(uint64_t S)
 {
-    return S != 0 && S < (1ull << 62);
+    return S - 1 < (1ull << 62) - 1;
 }
 
 // FP64 value: s = RNE(S) 2^-62, r = sigma sqrt(-2 ln(s) / s), no fused ops.
@@ -297,24 +312,12 @@ __device__ __forceinline__ uint32_t rank_below(uint64_t m)
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
-__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v)
+// Lane l's value of v (l wave-uniform).
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, int l)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1)
-        v += (uint64_t)__shfl_xor((unsigned long long)v, o, 64);
-    return v;
-}
-
-// Sum of v over lanes 0 .. k-1 (k wave-uniform, at most 64), read lane by
-// lane into scalar registers; cheaper in registers than a shuffle tree when k
-// is small, which is the common case of the look-back.
-__device__ __forceinline__ uint64_t lane_sum(uint64_t v, int k)
-{
-    const uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
-    uint64_t acc = 0;
-    for (int i = 0; i < k; ++i)
-        acc += ((uint64_t)__builtin_amdgcn_readlane(hi, i) << 32) | __builtin_amdgcn_readlane(lo, i);
-    return acc;
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, l);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(v >> 32), l);
+    return ((uint64_t)hi << 32) | lo;
 }
 
 __device__ __forceinline__ uint64_t uniform_u64(uint64_t v)
@@ -324,160 +327,15 @@ __device__ __forceinline__ uint64_t uniform_u64(uint64_t v)
     return ((uint64_t)hi << 32) | lo;
 }
 
-// ---------------------------------------------------------------------------
-// Look-back status words (one per tile): [63:42] launch tag, [41:40] flag
-// (1 = tile aggregate, 2 = inclusive prefix), [39:0] accepted-pair count.
-// Accessed only with relaxed agent-scope atomics: the word carries all the
-// information, so no other memory needs to be ordered with it.
-// ---------------------------------------------------------------------------
-constexpr uint64_t ST_AGG = 1, ST_INC = 2;
-constexpr uint64_t ST_VAL_MASK = (1ull << 40) - 1;
-
-__device__ __forceinline__ uint64_t st_pack(uint32_t tag, uint64_t flag, uint64_t val)
+// Orders one wave's LDS accesses before and after this point for all of its
+// lanes: a lane may then read what other lanes of the wave wrote.  The
+// fences keep the compiler from moving or forwarding LDS accesses across it
+// (a wave's LDS instructions execute in order in hardware).
+__device__ __forceinline__ void wave_lds_sync()
 {
-    return ((uint64_t)tag << 42) | (flag << 40) | (val & ST_VAL_MASK);
-}
-
-__device__ __forceinline__ void st_publish(uint64_t* p, uint64_t w)
-{
-    __hip_atomic_store(p, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ uint64_t st_read(const uint64_t* p)
-{
-    return __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// One window of a look-back: items i = 0 .. k-1 (k <= 64) are predecessors,
-// nearest first; lane i polls item i through probe(i, valid, inc, val).
-// Items go from invalid to valid, and a valid item is either an aggregate
-// (its own count) or inclusive (the prefix up to and including it).  The
-// window is resolved once every item up to the nearest inclusive one is
-// valid: the result is the sum of their values, and `found` tells whether an
-// inclusive item ended the sum.  An item still missing after spin_limit polls
-// is resolved by help(i), which returns its value and whether it is
-// inclusive -- so the look-back never depends on another wave making
-// progress.  Called by all 64 lanes of a wave; results are wave-uniform.
-struct Resolved {
-    uint64_t val;
-    bool inc;
-};
-
-template <typename Probe, typename Help>
-__device__ __forceinline__ uint64_t window_sum(uint32_t k, uint32_t spin_limit, bool& found, Probe&& probe,
-                                               Help&& help)
-{
-    const uint32_t lane = lane_id();
-    const uint64_t kmask = k >= 64 ? ~0ull : ((1ull << k) - 1);
-    uint64_t acc = 0;
-    uint32_t base = 0;     // items below base are already in acc
-    uint32_t spins = 0;
-    for (;;) {
-        bool valid = true, inc = false;
-        uint64_t val = 0;
-        if (lane >= base && lane < k)
-            probe(lane, valid, inc, val);
-        const uint64_t vmask = __ballot(valid) | ~kmask;
-        const uint64_t imask = __ballot(valid && inc) & kmask;
-        const int first = imask ? (int)__builtin_ctzll(imask) : 64;
-        const uint64_t need = first >= 63 ? ~0ull : ((2ull << first) - 1);
-        if ((vmask & need) == need) {
-            acc += lane_sum(val, first < 64 ? first + 1 : (int)k);
-            found = first < 64;
-            return acc;
-        }
-        if (++spins > spin_limit) {
-            // items base .. m-1 are valid aggregates (an inclusive one among
-            // them would have satisfied the test above)
-            const uint32_t m = (uint32_t)__builtin_ctzll(~vmask);
-            acc += lane_sum(val, (int)m);
-            const Resolved r = help(m);
-            acc += r.val;
-            if (r.inc) {
-                found = true;
-                return acc;
-            }
-            base = m + 1;
-            spins = 0;
-            if (base >= k) {
-                found = false;
-                return acc;
-            }
-        } else {
-            __builtin_amdgcn_s_sleep(1);
-        }
-    }
-}
-
-// Two-level decoupled look-back for tile lt of a stream (local indices).
-//   st0[t]   tile status words: the tile's count (aggregate), later its
-//            inclusive prefix;
-//   bst0[b]  block status words for blocks of 64 tiles: the block's count
-//            (aggregate), later the inclusive prefix at the block's end.
-// Both kinds are published by the last tile of each block, which reads its
-// 63 block-mates' words (one window) -- no atomic read-modify-write anywhere,
-// so nothing serialises on a shared address.  The exclusive prefix of tile
-// lt comes from at most one window over its own block and, per 64 earlier
-// blocks, one window of block words, independent of how many tiles are in
-// flight.  count_tile(t) recomputes a tile's count when its word is missing
-// for too long; a missing block word is rebuilt from the block's tiles.
-struct LookbackRef {
-    const uint64_t* st0;
-    uint64_t* bst0;
-    uint64_t nts;          // tiles in the stream
-};
-
-template <typename CountTile>
-__device__ __forceinline__ Resolved tiles_window(const LookbackRef& q, uint64_t top, uint32_t k, uint32_t tag,
-                                                 uint32_t spin_limit, CountTile&& count_tile)
-{
-    // tiles top-1, top-2, ..., top-k
-    bool found = false;
-    const uint64_t v = window_sum(
-        k, spin_limit, found,
-        [&](uint32_t i, bool& valid, bool& inc, uint64_t& val) {
-            const uint64_t w = st_read(q.st0 + (top - 1 - i) * kStatusStride);
-            valid = (uint32_t)(w >> 42) == tag && ((w >> 40) & 3) != 0;
-            inc = ((w >> 40) & 3) == ST_INC;
-            val = w & ST_VAL_MASK;
-        },
-        [&](uint32_t i) { return Resolved{count_tile(top - 1 - i), false}; });
-    return Resolved{v, found};
-}
-
-// Level 1 of the look-back: the prefix contributed by blocks b0-1, b0-2, ...
-// (64 block words per window).  Returns the sum up to the nearest inclusive
-// block word (or down to the stream's start).
-template <typename CountTile>
-__device__ __forceinline__ uint64_t lookback_blocks(const LookbackRef& q, uint64_t b0, uint32_t tag,
-                                                    uint32_t spin_limit, CountTile&& count_tile)
-{
-    uint64_t excl = 0;
-    int64_t pos = (int64_t)b0 - 1;
-    while (pos >= 0) {
-        const uint32_t k = pos + 1 >= 64 ? 64u : (uint32_t)(pos + 1);
-        bool found = false;
-        const int64_t top = pos;
-        excl += window_sum(
-            k, spin_limit, found,
-            [&](uint32_t i, bool& valid, bool& inc, uint64_t& val) {
-                const uint64_t w = st_read(q.bst0 + (uint64_t)(top - (int64_t)i) * kStatusStride);
-                valid = (uint32_t)(w >> 42) == tag && ((w >> 40) & 3) != 0;
-                inc = ((w >> 40) & 3) == ST_INC;
-                val = w & ST_VAL_MASK;
-            },
-            [&](uint32_t i) {
-                // rebuild block top - i from its tiles (last tile first)
-                const uint64_t b = (uint64_t)(top - (int64_t)i);
-                const uint64_t end = (b + 1) << 6;
-                const uint64_t e = end < q.nts ? end : q.nts;
-                return tiles_window(q, e, (uint32_t)(e - (b << 6)), tag, spin_limit, count_tile);
-            });
-        if (found)
-            return excl;
-        pos -= k;
-    }
-    return excl;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
 }  // namespace nrng

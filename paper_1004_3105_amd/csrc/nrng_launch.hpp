@@ -7,56 +7,51 @@
 
 namespace nrng {
 
-// Per-device control block of the look-back kernels.  It resets itself at
-// the end of every launch (the last workgroup to exit clears the exit
-// counter and advances the epoch), so consecutive launches and graph replays
-// need no memset.
-struct Ctl {
-    uint32_t unused;
-    uint32_t exited;     // workgroups that have finished
-    uint32_t epoch;      // tag of this launch's status words, 1 .. 2^22 - 1
-    uint32_t pad;
-    uint64_t consumed;   // single stream: uniforms consumed (for the cursor)
-};
-
-constexpr uint32_t kEpochLimit = 1u << 22;
-
-// Status words (tile and block) are spaced kStatusStride words apart, so that
-// the words of the tiles in flight at one moment spread over many memory
-// channels instead of sharing a few cache lines.
-#ifndef NRNG_STATUS_STRIDE
-#define NRNG_STATUS_STRIDE 1
-#endif
-constexpr uint64_t kStatusStride = NRNG_STATUS_STRIDE;
-
 enum Mode { MODE_SINGLE = 0, MODE_BATCHED = 1, MODE_TRACE = 2, MODE_XY = 3 };
 
+// The Polar method runs as three kernels over tiles of 64 U candidates
+// (U accept-mask words):
+//   mask      hash, exact predicate and ballots of every candidate of the
+//             budget; writes the mask words, each tile's accepted count as an
+//             exclusive prefix within its chunk of kChunkTiles tiles, and the
+//             chunk's total;
+//   scan      one workgroup: exclusive prefix of the chunk totals;
+//   generate  per tile, the accepted candidates are listed from the masks and
+//             the lanes of a wave each take consecutive accepted pairs, so
+//             that only accepted candidates are re-hashed and transformed and
+//             the output is written with aligned 16-byte stores.
+// No kernel waits on another workgroup, and consecutive launches and graph
+// replays need no clearing of the workspace.
+constexpr uint32_t kChunkTiles = 16;
+constexpr uint32_t kMaskWG = 256;
+
 struct PolarArgs {
-    // single stream / trace
+    // single stream / trace / xy
     uint64_t seed;
     uint64_t offset;
-    uint64_t *cursor;        // device cursor (nullable): offset = *cursor, advanced at the end
+    uint64_t *cursor;        // device cursor (nullable): offset = *cursor, advanced by the consumed count
     uint64_t n;              // normals to produce (single); ignored for trace / xy
-    uint32_t ntiles;         // single / trace / xy: look-back tile budget
+    uint64_t nwords;         // single / trace / xy: candidate budget in 64-candidate words
+    uint64_t ntiles;         // single / trace / xy: tiles of the budget
     double mu, sigma;
     void *out;
     uint64_t *consumed;      // single: device pointer (nullable)
     // batched
     uint32_t nstreams;
-    const uint64_t *tile_start;   // nstreams + 1 entries (workspace, built on the device)
+    const uint64_t *tile_start;    // nstreams + 1 entries (built on the device by prep_kernel)
+    const uint64_t *stream_words;  // nstreams entries: candidate budget of each stream, in words
     const uint64_t *seeds, *offsets, *ns, *out_off;
     const double *mus, *sigmas;
     uint64_t *consumed_arr;
-    const uint64_t *block_start;  // batched: nstreams + 1 entries, first block of each stream
     // workspace
-    uint64_t *status;
-    uint64_t status_cap;
-    uint64_t *bst;           // block status words (tagged), bcap entries
-    uint64_t bcap;
-    Ctl *ctl;
+    uint64_t *masks;         // accept-mask words, tile t's words at [t U, t U + U)
+    uint32_t *ipfx;          // per tile: accepted pairs before it within its chunk
+    uint32_t *csum;          // per chunk: accepted pairs in it
+    uint64_t *cpfx;          // per chunk: accepted pairs before it (all streams together)
+    uint64_t *misc;          // [0]: the single-stream offset read from *cursor by the scan kernel
     // trace / explicit candidates
     uint64_t ncand;
-    uint64_t *masks, *word_prefix;
+    uint64_t *word_prefix;
     const int32_t *xy;
     uint64_t *count_out;
 };
@@ -79,11 +74,11 @@ struct PrepArgs {
     uint32_t nstreams;
     const uint64_t *ns, *out_off;    // out_off nullable (packed)
     uint64_t out_len;
-    uint64_t unit;                   // B1: pairs per tile; Polar: candidates per tile
-    uint64_t status_cap;             // Polar: capacity in tiles
-    uint64_t block_cap;              // Polar: capacity in blocks of 64 tiles
+    uint64_t unit;                   // B1: pairs per tile; Polar: mask words per tile
+    uint64_t word_cap;               // Polar: workspace capacity in mask words (tiles x unit)
+    uint64_t tile_cap;               // Polar: workspace capacity in tiles
     uint64_t *tile_start;            // out: nstreams + 1
-    uint64_t *block_start;           // out (Polar): nstreams + 1
+    uint64_t *stream_words;          // out (Polar): nstreams, candidate budget in words
     uint64_t *packed_off;            // out: nstreams (used when out_off is null)
     uint64_t *consumed;              // out (nullable)
 };
@@ -97,29 +92,32 @@ int polar_variants(const Variant **v);
 int launch_b1_single(int dtype, int vi, const B1Args &a, uint32_t grid, hipStream_t s);
 int launch_b1_words(int dtype, const B1Args &a, uint64_t npairs, hipStream_t s);
 int launch_b1_batched(int dtype, int vi, const B1Args &a, uint32_t grid, hipStream_t s);
-int launch_polar(int mode, int dtype, int vi, const PolarArgs &a, uint32_t grid, hipStream_t s);
+// Polar: the mask, scan and generate kernels, in that order on stream s.
+// grid_mask / grid_gen are the persistent grid sizes of the first and last.
+int launch_polar(int mode, int dtype, int vi, const PolarArgs &a, uint32_t grid_mask, uint32_t grid_gen,
+                 hipStream_t s);
 int launch_prep(const PrepArgs &a, hipStream_t s);
-int occupancy_polar(int mode, int dtype, int vi, int *blocks_per_cu);
+int occupancy_polar(int mode, int dtype, int vi, int *blocks_per_cu);        // generate kernel
+int occupancy_polar_mask(int mode, int vi, int *blocks_per_cu);
 int occupancy_b1(int batched, int dtype, int vi, int *blocks_per_cu);
 int launch_probe_store(void *out, uint64_t nbytes, uint32_t grid, hipStream_t s);
 int launch_probe_copy(void *dst, const void *src, uint64_t nbytes, uint32_t grid, hipStream_t s);
 int launch_probe_hash(uint64_t seed, uint64_t nhash, uint64_t *sink, uint64_t sink_len, uint32_t grid,
                       hipStream_t s);
 
-// Tiles of the Polar look-back budget for a stream of npairs accepted pairs,
-// with `cand` candidates per tile: the expected candidate count
-// npairs / (pi/4), plus four standard deviations of the negative-binomial
-// count, plus 64.  Exceeding the budget is not an error (the last tile of
-// the stream continues serially); the budget only sizes the look-back.
-__host__ __device__ inline uint64_t polar_budget_tiles(uint64_t npairs, uint64_t cand)
+// Candidate budget of a Polar stream of npairs accepted pairs, in words of
+// 64 candidates: the expected candidate count npairs / (pi/4), plus four
+// standard deviations of the negative-binomial count, plus 64.  Exceeding
+// the budget is not an error (the stream's last tile continues serially past
+// it); the budget only sizes the mask pass.
+__host__ __device__ inline uint64_t polar_budget_words(uint64_t npairs)
 {
     if (npairs == 0)
         return 0;
     const double p = 0.78539816339744830962, q = 1.0 - p;
     const double P = (double)npairs;
     const double c = P / p + 4.0 * sqrt(P * q) / p + 64.0;
-    uint64_t t = (uint64_t)(c / (double)cand) + 1;
-    return t;
+    return (uint64_t)(c / 64.0) + 1;
 }
 
 }  // namespace nrng

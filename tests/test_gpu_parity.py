@@ -146,18 +146,20 @@ def test_polar_xy_edge_cases(dtype):
 
 
 def test_polar_budget_continuation():
-    """A stream that outgrows its tile budget continues serially in its last
-    budget tile; the result is the same stream."""
+    """A stream that outgrows its candidate budget continues serially past it
+    in its last tile; the result is the same stream.  Budgets below, at and
+    above the need (about 995 words of 64 candidates here), ending inside and
+    at the end of a tile."""
     d = dev()
     n = 100001
     ref, cons = run("polar", 3, 1, n, nb.NRNG_F32, with_consumed=True)
-    for tiles in (1, 2, 5, 40):
+    for words in (1, 2, 33, 500, 990, 994, 995, 996, 1024, 1100):
         out = torch.empty(n, dtype=torch.float32, device=d)
         c = torch.zeros(1, dtype=torch.int64, device=d)
-        case("polar budget", tiles)
-        nb.nrng_test_polar_budget(3, 1, n, 0.0, 1.0, out, nb.NRNG_F32, tiles, None, c)
+        case("polar budget", words)
+        nb.nrng_test_polar_budget(3, 1, n, 0.0, 1.0, out, nb.NRNG_F32, words, None, c)
         torch.cuda.synchronize()
-        assert torch.equal(out, ref), tiles
+        assert torch.equal(out, ref), words
         assert int(c.item()) == cons
 
 
