@@ -32,7 +32,34 @@ sys.path.insert(0, ROOT)
 
 METRIC = "normals/s and % HBM write peak, FP32 batched vs plain FP64 (B1, Polar)"
 HBM_PEAK_GBS = 8000.0          # MI355X datasheet HBM3E bandwidth
+# VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.32e12 lane
+# operations/s (the published 157.3 TFLOP/s FP32 vector figure counts an FMA
+# as 2 flops on 2 packed values: 157.3 / 4)
+VALU_PEAK_TOPS = 39.32
+# Algorithmic VALU lane operations per unit of work of each kernel: the
+# 32-bit VALU operations the method's arithmetic needs, counted step by step
+# (64-bit add 1, 64-bit shift 1, 64-bit xor 2, 64 x 64 -> 64 multiply 4,
+# high word of a 64 x 64 multiply 4, conversions, compares, selects, FMAs and
+# each transcendental 1).  SplitMix64: full 18, top word only 17.
+#   polar_count:    per candidate: 2 hashes (top words) 34 + X^2 + Y^2 2 +
+#                   0 < S < 2^62 test 2
+#   polar_generate: per pair: 2 hashes 34 + S 2 + the FP32 radius with the
+#                   exact complement near s = 1 (complement and select 5,
+#                   conversion 4, remainder and selects 7, log / rcp / sqrt
+#                   3, scalings 4) 23 + 2 conversions and 2 FMAs 4
+#   b1_batched:     per pair: hash of u 18 + hash of v (top word) 17 +
+#                   ln(1 - u) with the exact complement 21 + angle reduction,
+#                   conversion, sin, cos 9 + 2 FMAs
+ALU_OPS = {"polar_count": 38, "polar_generate": 63, "b1_batched": 67}
+ALU_UNIT = {"polar_count": "candidate", "polar_generate": "output pair", "b1_batched": "output pair"}
+KERNEL_NAMES = {"polar_count": "polar_mask_kernel<MODE_BATCHED> + polar_scan_kernel",
+                "polar_generate": "polar_gen_kernel<float, MODE_BATCHED>",
+                "b1_batched": "b1_batched_kernel<float>"}
 PROFILES = os.path.join(ROOT, "profiles")
+
+
+def u64sum(t) -> int:
+    return int(t.cpu().numpy().view("uint64").sum(dtype="uint64"))
 
 
 def kernel_source_hash() -> str:
@@ -121,24 +148,27 @@ def main() -> int:
     cons = {name: torch.zeros(ns, dtype=torch.int64, device=dev) for name, _ in methods}
     nb.nrng_reserve(total, ns)
 
+    # Each method: plan (set-up kernel), then exec.  Exec is launched as its
+    # two parts so that events separate the kernels: for Polar, part 1 = the
+    # mask and scan kernels, part 2 = the generate kernel; for B1 part 1 is
+    # empty and part 2 is the B1 kernel.  Per method 4 events.
     def step(evs=None):
-        k = 0
-        for name, m in methods:
+        for i, (name, m) in enumerate(methods):
             if evs is not None:
-                evs[k].record(stream)
+                evs[4 * i].record(stream)
             nb.nrng_batched_plan(m, ns, D["n"], None, total, nb.NRNG_F32, stream, cons[name])
+            for part in (1, 2):
+                if evs is not None:
+                    evs[4 * i + part].record(stream)
+                nb.nrng_batched_exec_part(part, m, ns, D["seed"], D["offset"], D["n"], None, D["mu"], D["sigma"],
+                                          outs[name], nb.NRNG_F32, stream, cons[name])
             if evs is not None:
-                evs[k + 1].record(stream)
-            nb.nrng_batched_exec(m, ns, D["seed"], D["offset"], D["n"], None, D["mu"], D["sigma"], outs[name],
-                                 nb.NRNG_F32, stream, cons[name])
-            k += 2
-        if evs is not None:
-            evs[k].record(stream)
+                evs[4 * i + 3].record(stream)
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    nev = 2 * len(methods) + 1
+    nev = 4 * len(methods)
     events = [[torch.cuda.Event(enable_timing=True) for _ in range(nev)] for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -149,26 +179,41 @@ def main() -> int:
     elapsed = t1 - t0
     normals = total * len(methods) * args.steps
     value = normals / elapsed
+
+    pairs = int(sum((int(x) + 1) // 2 for x in cfg["n"]))
     per_kernel = {}
     for i, (name, _) in enumerate(methods):
-        plan_ms = [events[s][2 * i].elapsed_time(events[s][2 * i + 1]) for s in range(args.steps)]
-        exec_ms = [events[s][2 * i + 1].elapsed_time(events[s][2 * i + 2]) for s in range(args.steps)]
-        ms = sum(exec_ms) / len(exec_ms)
-        gbs = 4.0 * total / (ms * 1e-3) / 1e9
-        per_kernel[name] = {"plan_ms": round(sum(plan_ms) / len(plan_ms), 5), "exec_ms": round(ms, 5),
-                            "exec_median_ms": round(median(exec_ms), 5),
-                            "normals_per_s": total / (ms * 1e-3), "write_GBps": round(gbs, 1),
+        def avg(a, b):
+            return sum(events[s][4 * i + a].elapsed_time(events[s][4 * i + b]) for s in range(args.steps)) / args.steps
+        plan_ms, count_ms, gen_ms = avg(0, 1), avg(1, 2), avg(2, 3)
+        exec_ms = count_ms + gen_ms
+        gbs = 4.0 * total / (exec_ms * 1e-3) / 1e9
+        per_kernel[name] = {"plan_ms": round(plan_ms, 5), "exec_ms": round(exec_ms, 5),
+                            "normals_per_s": total / (exec_ms * 1e-3), "write_GBps": round(gbs, 1),
                             "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)}
+        if name == "polar":
+            cand = int(u64sum(cons[name])) // 2       # candidates the method evaluates
+            per_kernel[name]["count_ms"] = round(count_ms, 5)
+            per_kernel[name]["generate_ms"] = round(gen_ms, 5)
+            per_kernel[name]["candidates"] = cand
+            units = {"polar_count": (count_ms, ALU_OPS["polar_count"] * cand),
+                     "polar_generate": (gen_ms, ALU_OPS["polar_generate"] * pairs)}
+        else:
+            units = {"b1_batched": (gen_ms, ALU_OPS["b1_batched"] * pairs)}
+        for k, (ms, ops) in units.items():
+            per_kernel[name].setdefault("alu", {})[k] = {
+                "ms": round(ms, 5), "Tops_per_s": round(ops / (ms * 1e-3) / 1e12, 2),
+                "frac_valu_peak": round(ops / (ms * 1e-3) / 1e12 / VALU_PEAK_TOPS, 4)}
 
-    # dominant kernel -> roofline
-    dom = max(per_kernel, key=lambda k: per_kernel[k]["exec_ms"])
-    tag = "batched_%s_f32" % dom
-    achieved = per_kernel[dom]["write_GBps"]
-    traffic = read_traffic(tag)
-    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "polar_kernel<float,MODE_BATCHED>" if dom == "polar" else "b1_batched_kernel<float>",
-                "algorithmic_bytes_per_launch": 4 * total}
+    # dominant kernel -> roofline (ALU-bound: VALU lane operations)
+    kern = {k: v for pk in per_kernel.values() for k, v in pk["alu"].items()}
+    dom = max(kern, key=lambda k: kern[k]["ms"])
+    traffic = read_traffic("batched_%s_f32" % dom)
+    roofline = {"bound": "alu", "achieved": kern[dom]["Tops_per_s"], "peak": VALU_PEAK_TOPS,
+                "unit": "Tlane-op/s", "frac": kern[dom]["frac_valu_peak"], "traffic": traffic,
+                "kernel": KERNEL_NAMES[dom], "ms_per_launch": kern[dom]["ms"],
+                "ops_per_unit": ALU_OPS[dom], "unit_of_work": ALU_UNIT[dom],
+                "algorithmic_write_bytes_per_launch": 4 * total}
 
     result = {
         "metric": METRIC,

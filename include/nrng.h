@@ -172,12 +172,24 @@ int nrng_batched(int method, uint32_t nstreams, const uint64_t *d_seed, const ui
  * dtype, launch variant, stream count and layout (packed or not); d_n and
  * d_out_off must hold the values the plan saw.  A plan stays valid until the
  * next plan or batched call on the device.  nrng_batched(...) is
- * plan + exec. */
+ * plan + exec.
+ * nrng_batched_exec_part runs one half of exec's launch sequence, for timing
+ * and profiling the kernels separately: part 1 = the Polar mask and scan
+ * kernels (nothing for B1), part 2 = the Polar generate kernel (the B1
+ * kernel for B1), part 0 = both (identical to nrng_batched_exec).  Part 2
+ * reads what part 1 of the same plan left in the workspace, so it must
+ * follow it on the same stream with no other Polar call in between.  Same
+ * arguments and errors as nrng_batched_exec, plus NRNG_EINVAL for a part
+ * outside 0..2. */
 int nrng_batched_plan(int method, uint32_t nstreams, const uint64_t *d_n, const uint64_t *d_out_off,
                       uint64_t out_len, int dtype, void *stream, uint64_t *d_consumed);
 int nrng_batched_exec(int method, uint32_t nstreams, const uint64_t *d_seed, const uint64_t *d_offset,
                       const uint64_t *d_n, const uint64_t *d_out_off, const double *d_mu, const double *d_sigma,
                       void *out, int dtype, void *stream, uint64_t *d_consumed);
+int nrng_batched_exec_part(int part, int method, uint32_t nstreams, const uint64_t *d_seed,
+                           const uint64_t *d_offset, const uint64_t *d_n, const uint64_t *d_out_off,
+                           const double *d_mu, const double *d_sigma, void *out, int dtype, void *stream,
+                           uint64_t *d_consumed);
 
 /* ------------------------------------------------------------------------
  * Repeated fills through a HIP graph: capture one nrng_polar_dev launch

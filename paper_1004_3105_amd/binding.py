@@ -37,6 +37,7 @@ _SIGS = {
     "nrng_batched": (_i32, [_i32, _u32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _u64, _i32, _vp, _vp]),
     "nrng_batched_plan": (_i32, [_i32, _u32, _vp, _vp, _u64, _i32, _vp, _vp]),
     "nrng_batched_exec": (_i32, [_i32, _u32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp]),
+    "nrng_batched_exec_part": (_i32, [_i32, _i32, _u32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp]),
     "nrng_fillgraph_create": (_i32, [_u64, _vp, _u64, _f64, _f64, _vp, _i32, _vp, ctypes.POINTER(_vp)]),
     "nrng_fillgraph_launch": (_i32, [_vp, _vp]),
     "nrng_fillgraph_destroy": (_i32, [_vp]),
@@ -186,6 +187,17 @@ def nrng_batched_exec(method, nstreams, d_seed, d_offset, d_n, d_out_off, d_mu, 
     _check("nrng_batched_exec", lib().nrng_batched_exec(method, nstreams, _ptr(d_seed), _ptr(d_offset), _ptr(d_n),
                                                         _ptr(d_out_off), _ptr(d_mu), _ptr(d_sigma), _ptr(out),
                                                         dtype, _stream(stream), _ptr(d_consumed)))
+
+
+def nrng_batched_exec_part(part, method, nstreams, d_seed, d_offset, d_n, d_out_off, d_mu, d_sigma, out, dtype,
+                           stream=None, d_consumed=None) -> None:
+    for t, nm in ((d_seed, "d_seed"), (d_offset, "d_offset"), (d_n, "d_n"), (d_out_off, "d_out_off"),
+                  (d_mu, "d_mu"), (d_sigma, "d_sigma"), (d_consumed, "d_consumed")):
+        _need(t, 8 * nstreams, "nrng_batched_exec_part " + nm)
+    _check("nrng_batched_exec_part",
+           lib().nrng_batched_exec_part(part, method, nstreams, _ptr(d_seed), _ptr(d_offset), _ptr(d_n),
+                                        _ptr(d_out_off), _ptr(d_mu), _ptr(d_sigma), _ptr(out), dtype,
+                                        _stream(stream), _ptr(d_consumed)))
 
 
 def nrng_fillgraph_create(seed, d_cursor, n, mu, sigma, out, dtype, stream) -> int:

@@ -49,12 +49,14 @@ struct Tune {
 
 std::mutex g_mu;
 DevState g_dev[kMaxDev];
-// Defaults chosen by the autotuner on MI355X (see the tune table written by
-// the Python autotuner); kernel ids: 0 = B1 single, 1 = Polar, 2 = B1 batched.
+// Defaults chosen by the autotuner on MI355X (paper_1004_3105_amd/autotune.py,
+// table tune_gfx950.json); [kernel][dtype], kernel ids: 0 = B1 single,
+// 1 = Polar, 2 = B1 batched; dtype order F64, F32, BF16, F16; entries are
+// {variant index, grid cap per CU (0 = occupancy)}.
 Tune g_tune[3][4] = {
-    {{1, 0}, {1, 0}, {1, 0}, {1, 0}},
-    {{1, 0}, {1, 0}, {1, 0}, {1, 0}},
-    {{1, 0}, {1, 0}, {1, 0}, {1, 0}},
+    {{1, 0}, {3, 4}, {3, 0}, {2, 0}},
+    {{1, 0}, {1, 0}, {3, 0}, {3, 0}},
+    {{2, 0}, {2, 0}, {2, 0}, {2, 0}},
 };
 
 inline hipStream_t S(void *s) { return reinterpret_cast<hipStream_t>(s); }
@@ -531,6 +533,17 @@ int nrng_batched_exec(int method, uint32_t nstreams, const uint64_t *d_seed, con
                       const uint64_t *d_n, const uint64_t *d_out_off, const double *d_mu, const double *d_sigma,
                       void *out, int dtype, void *stream, uint64_t *d_consumed)
 {
+    return nrng_batched_exec_part(0, method, nstreams, d_seed, d_offset, d_n, d_out_off, d_mu, d_sigma, out, dtype,
+                                  stream, d_consumed);
+}
+
+int nrng_batched_exec_part(int part, int method, uint32_t nstreams, const uint64_t *d_seed,
+                           const uint64_t *d_offset, const uint64_t *d_n, const uint64_t *d_out_off,
+                           const double *d_mu, const double *d_sigma, void *out, int dtype, void *stream,
+                           uint64_t *d_consumed)
+{
+    if (part < 0 || part > 2)
+        return NRNG_EINVAL;
     if (!dtype_ok(dtype))
         return NRNG_EDTYPE;
     if (method != NRNG_METHOD_B1 && method != NRNG_METHOD_POLAR)
@@ -567,6 +580,8 @@ int nrng_batched_exec(int method, uint32_t nstreams, const uint64_t *d_seed, con
         a.out_off = off;
         a.mus = d_mu;
         a.sigmas = d_sigma;
+        if (part == 1)
+            return NRNG_OK;   // B1 has no count pass
         const uint32_t grid = persistent_grid(*d, b1_blocks_per_cu(*d, 1, dtype, tu.vi), tu.grid_per_cu, 0);
         return hip_status(launch_b1_batched(dtype, tu.vi, a, grid, s));
     }
@@ -587,7 +602,7 @@ int nrng_batched_exec(int method, uint32_t nstreams, const uint64_t *d_seed, con
     const uint32_t gm = persistent_grid(*d, polar_mask_blocks_per_cu(*d, MODE_BATCHED, tu.vi), 0, 0);
     const uint32_t gg =
         persistent_grid(*d, polar_blocks_per_cu(*d, MODE_BATCHED, dtype, tu.vi), tu.grid_per_cu, 0);
-    return hip_status(launch_polar(MODE_BATCHED, dtype, tu.vi, a, gm, gg, s));
+    return hip_status(launch_polar(MODE_BATCHED, dtype, tu.vi, a, gm, gg, s, part));
 }
 
 int nrng_batched(int method, uint32_t nstreams, const uint64_t *d_seed, const uint64_t *d_offset,

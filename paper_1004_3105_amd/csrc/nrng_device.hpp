@@ -291,7 +291,7 @@ __device__ __forceinline__ float polar_r_small(uint64_t S, float sigma)
     return (float)__builtin_sqrt(q) * sigma;
 }
 
-__device__ __forceinline__ bool polar_small(uint64_t S) { return S < (1ull << 42); }
+__device__ __forceinline__ bool polar_small(uint64_t S) { return (uint32_t)(S >> 32) < (1u << 10); }   // S < 2^42
 
 __device__ __forceinline__ void polar_value_f32(int32_t X, int32_t Y, uint64_t S, float mu, float k2,
                                                 float sigma, float& zx, float& zy)

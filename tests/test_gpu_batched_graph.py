@@ -183,3 +183,30 @@ def test_polar_dev_under_torch_graph_capture():
         y = torch.ones(10, device=d) * r
         torch.cuda.synchronize()
         del y
+
+
+@pytest.mark.parametrize("method", [nb.NRNG_METHOD_B1, nb.NRNG_METHOD_POLAR])
+def test_exec_parts_equal_exec(method):
+    """The count half then the generate half of the exec sequence (the
+    timing hook) give exactly what exec gives; a part outside 0..2 is an
+    argument error."""
+    d = dev()
+    cfg = small_config(61)
+    D = to_dev(cfg, d)
+    ns = len(cfg["n"])
+    outs = []
+    for parts in ((0,), (1, 2)):
+        out = torch.full((cfg["total"],), float("nan"), dtype=torch.float32, device=d)
+        cons = torch.zeros(ns, dtype=torch.int64, device=d)
+        case("exec parts", method, parts)
+        nb.nrng_batched_plan(method, ns, D["n"], None, cfg["total"], nb.NRNG_F32, None, cons)
+        for p in parts:
+            nb.nrng_batched_exec_part(p, method, ns, D["seed"], D["offset"], D["n"], None, D["mu"], D["sigma"],
+                                      out, nb.NRNG_F32, None, cons)
+        torch.cuda.synchronize()
+        outs.append((out, u64(cons)))
+    assert torch.equal(outs[0][0], outs[1][0])
+    assert np.array_equal(outs[0][1], outs[1][1])
+    with pytest.raises(nb.NrngError):
+        nb.nrng_batched_exec_part(3, method, ns, D["seed"], D["offset"], D["n"], None, D["mu"], D["sigma"],
+                                  outs[0][0], nb.NRNG_F32, None, None)

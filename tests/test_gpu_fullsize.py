@@ -1,0 +1,189 @@
+"""Parity at the full sizes of the measured workloads, in the launch
+configuration the benchmark times (the library's tuned defaults), on outputs
+the oracle computes independently:
+
+* single streams of 2^30 FP32 normals (B1 seed 1, Polar seed 7): B1 at
+  sampled output indices, each pair from its own counters; Polar on whole
+  candidate chunks, placed by the oracle's own prefix of accepted counts,
+  plus the consumed count;
+* the batched workload of 4096 streams (about 4.4e8 normals per method):
+  every stream's consumed count, and sampled streams in full;
+* 64 graph-replayed fills of 2^28 FP32 Polar normals from one device cursor
+  (2^34 normals of one stream): the final cursor against the oracle's count,
+  and sampled slices of sampled fills, placed by the oracle's prefix, with
+  moments and a KS statistic over all the sampled values.
+"""
+import os
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import synth
+from gpu_util import assert_close, case, dev, host, u64
+from helpers import stat_bounds
+from paper_1004_3105_amd import binding as nb
+
+pytestmark = pytest.mark.gpu
+
+THREADS = min(16, os.cpu_count() or 1)
+CHUNK = 1 << 22          # candidate pairs per oracle count / window call
+
+
+class PolarIndex:
+    """The oracle's placement of a Polar stream: accepted counts of
+    consecutive candidate chunks and their exclusive prefix."""
+
+    def __init__(self, seed, offset, npairs):
+        self.seed, self.offset = seed, offset
+        ncand = int(npairs * 4 / np.pi * 1.0005) + (1 << 16)
+        while True:
+            counts = O.polar_chunk_counts(seed, offset, ncand, CHUNK, THREADS)
+            if counts.sum() >= npairs:
+                break
+            ncand += ncand // 8
+        self.ncand = ncand
+        self.pref = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+
+    def chunk_of_pair(self, a):
+        return int(np.searchsorted(self.pref, a, side="right")) - 1
+
+    def window(self, c, mu=0.0, sigma=1.0):
+        """Values of the accepted pairs of chunk c, and the first output
+        pair index they occupy."""
+        c0 = c * CHUNK
+        vals = O.polar_window(self.seed, self.offset, c0, min(CHUNK, self.ncand - c0), mu, sigma)
+        return vals, int(self.pref[c])
+
+    def consumed(self, npairs):
+        """Uniforms consumed by a stream of npairs pairs: 2 (j + 1) for the
+        candidate j that supplies pair npairs - 1."""
+        c = self.chunk_of_pair(npairs - 1)
+        c0 = c * CHUNK
+        masks, _, _ = O.polar_trace(self.seed, self.offset + 2 * c0, min(CHUNK, self.ncand - c0))
+        bits = np.unpackbits(masks.view(np.uint8), bitorder="little")
+        j = c0 + int(np.flatnonzero(bits)[npairs - 1 - int(self.pref[c])])
+        return 2 * (j + 1)
+
+
+def test_b1_single_stream_2e30_sampled():
+    d = dev()
+    n = 1 << 30
+    out = torch.empty(n, dtype=torch.float32, device=d)
+    case("b1 f32 single stream", n)
+    nb.nrng_boxmuller(1, 0, n, 0.0, 1.0, out, nb.NRNG_F32)
+    torch.cuda.synchronize()
+    idx = np.concatenate([np.arange(64), n - 64 + np.arange(64),
+                          synth.rng(31).integers(0, n, 8192)]).astype(np.int64)
+    got = host(out[torch.from_numpy(idx).to(d)])
+    assert_close(got, O.b1_at(1, 0, idx), nb.NRNG_F32, what="b1 2^30 sampled")
+
+
+def test_polar_single_stream_2e30_sampled():
+    d = dev()
+    n = 1 << 30
+    P = n // 2
+    out = torch.empty(n, dtype=torch.float32, device=d)
+    cons = torch.zeros(1, dtype=torch.int64, device=d)
+    case("polar f32 single stream", n)
+    nb.nrng_polar(7, 0, n, 0.0, 1.0, out, nb.NRNG_F32, None, cons)
+    torch.cuda.synchronize()
+    ix = PolarIndex(7, 0, P)
+    assert int(u64(cons)[0]) == ix.consumed(P)
+    last = ix.chunk_of_pair(P - 1)
+    chunks = sorted({0, last} | set(synth.rng(32).integers(0, last, 10).tolist()))
+    for c in chunks:
+        vals, a0 = ix.window(c)
+        m = min(vals.size, n - 2 * a0)
+        got = host(out[2 * a0:2 * a0 + m])
+        assert_close(got, vals[:m], nb.NRNG_F32, what="polar 2^30 chunk %d" % c)
+
+
+@pytest.mark.parametrize("method", [nb.NRNG_METHOD_B1, nb.NRNG_METHOD_POLAR])
+def test_batched_full_workload_sampled(method):
+    d = dev()
+    cfg = synth.batched_streams()
+    ns, total = len(cfg["n"]), cfg["total"]
+    D = {k: torch.from_numpy(cfg[k].view(np.int64) if cfg[k].dtype == np.uint64 else cfg[k]).to(d)
+         for k in ("seed", "offset", "n", "mu", "sigma")}
+    out = torch.empty(total, dtype=torch.float32, device=d)
+    cons = torch.zeros(ns, dtype=torch.int64, device=d)
+    nb.nrng_reserve(total, ns)
+    case("batched full workload", method, ns, total)
+    nb.nrng_batched(method, ns, D["seed"], D["offset"], D["n"], None, D["mu"], D["sigma"], out, total,
+                    nb.NRNG_F32, None, cons)
+    torch.cuda.synchronize()
+    c = u64(cons)
+    n = cfg["n"].astype(np.int64)
+    if method == nb.NRNG_METHOD_B1:
+        assert np.array_equal(c, (2 * ((n + 1) // 2)).astype(np.uint64))
+    order = np.argsort(n)
+    pick = sorted({int(order[0]), int(order[-1]), int(order[ns // 2])} |
+                  set(synth.rng(33).integers(0, ns, 24).tolist()))
+    fn = O.b1 if method == nb.NRNG_METHOD_B1 else O.polar
+    for j in pick:
+        o0 = int(cfg["out_off"][j])
+        ref, used = fn(int(cfg["seed"][j]), 0, int(n[j]), float(cfg["mu"][j]), float(cfg["sigma"][j]))
+        assert int(c[j]) == used, j
+        assert_close(host(out[o0:o0 + int(n[j])]), ref, nb.NRNG_F32, float(cfg["mu"][j]), float(cfg["sigma"][j]),
+                     what="batched stream %d" % j)
+    if method == nb.NRNG_METHOD_POLAR:
+        # every stream's consumed count: at least the minimum 2 ceil(n/2),
+        # even, and (for the sampled streams above) exactly the oracle's
+        assert np.all(c >= (2 * ((n + 1) // 2)).astype(np.uint64)) and np.all(c % 2 == 0)
+
+
+def test_graph_fill_64_x_2e28_sampled():
+    d = dev()
+    nf, fills = 1 << 28, 64
+    slen, per_fill, sampled_fills = 1 << 16, 4, 16
+    s = torch.cuda.Stream()
+    cursor = torch.zeros(1, dtype=torch.int64, device=d)
+    out = torch.empty(nf, dtype=torch.float32, device=d)
+    nb.nrng_reserve(nf, 0)
+    fsel = set(synth.rng(34).choice(fills, sampled_fills, replace=False).tolist()) | {0, fills - 1}
+    starts = {f: synth.slice_starts(per_fill, slen, nf, seed=0x51CE + f) for f in fsel}
+    samples = {}
+    case("graph fill create", nf)
+    g = nb.nrng_fillgraph_create(7, cursor, nf, 0.0, 1.0, out, nb.NRNG_F32, s)
+    try:
+        for f in range(fills):
+            nb.nrng_fillgraph_launch(g, s)
+            if f in fsel:
+                s.synchronize()
+                samples[f] = [host(out[st:st + slen]) for st in starts[f]]
+        s.synchronize()
+    finally:
+        nb.nrng_fillgraph_destroy(g)
+    ix = PolarIndex(7, 0, fills * nf // 2)
+    assert int(u64(cursor)[0]) == ix.consumed(fills * nf // 2)
+
+    def reference(f, st):
+        a = (f * nf + int(st)) // 2            # first output pair of the slice
+        b = a + slen // 2
+        ref = []
+        c = ix.chunk_of_pair(a)
+        while True:
+            vals, a0 = ix.window(c)
+            lo, hi = max(a, a0), min(b, a0 + vals.size // 2)
+            if hi > lo:
+                ref.append(vals[2 * (lo - a0):2 * (hi - a0)])
+            if a0 + vals.size // 2 >= b:
+                return np.concatenate(ref)
+            c += 1
+
+    jobs = [(f, st, got) for f in sorted(samples) for st, got in zip(starts[f], samples[f])]
+    with ThreadPoolExecutor(max_workers=THREADS) as ex:
+        refs = list(ex.map(lambda j: reference(j[0], j[1]), jobs))
+    allv = []
+    for (f, st, got), ref in zip(jobs, refs):
+        assert_close(got, ref, nb.NRNG_F32, what="fill %d slice at %d" % (f, st))
+        allv.append(got)
+    z = np.concatenate(allv)
+    bd = stat_bounds(z.size)
+    m = O.moments(z)
+    assert abs(m[0]) < bd["mean"] and abs(m[1] - 1) < bd["var"]
+    assert abs(m[2]) < bd["skew"] and abs(m[3] - 3) < bd["kurt"]
+    assert O.ks_normal(z) < bd["ks"]
