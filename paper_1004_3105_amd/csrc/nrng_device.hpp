@@ -312,6 +312,18 @@ __device__ __forceinline__ uint32_t rank_below(uint64_t m)
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
+// Sixteen dwords at the wave-uniform address p, through the scalar unit
+// (p 4-byte aligned, written by an earlier kernel).  The compiler only uses
+// scalar loads for memory it can prove unmodified; this one is written out,
+// and waits for its data before the block ends.
+typedef uint32_t u32x16 __attribute__((ext_vector_type(16)));
+__device__ __forceinline__ u32x16 scalar_load16(const void *p)
+{
+    u32x16 r;
+    asm volatile("s_load_dwordx16 %0, %1, 0x0\n\ts_waitcnt lgkmcnt(0)" : "=s"(r) : "s"(p) : "memory");
+    return r;
+}
+
 // Lane l's value of v (l wave-uniform).
 __device__ __forceinline__ uint64_t readlane64(uint64_t v, int l)
 {
