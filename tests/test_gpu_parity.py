@@ -11,7 +11,7 @@ import torch
 
 import oracle as O
 import synth
-from gpu_util import TDT, assert_close, case, dev, host, run, u64
+from gpu_util import NAME, TDT, assert_close, case, dev, host, run, u64
 from paper_1004_3105_amd import binding as nb
 
 pytestmark = pytest.mark.gpu
@@ -226,3 +226,26 @@ def test_gpu_output_distribution(method):
     assert abs(stats.skew(z)) < bd["skew"]
     assert abs(stats.kurtosis(z, fisher=False) - 3) < bd["kurt"]
     assert stats.kstest(z, "norm").statistic < bd["ks"]
+
+
+# ------------------------------------------------------------------ error report per dtype
+def test_error_report_per_dtype(capsys):
+    """The error against the FP64 oracle, per method and output dtype, on the
+    first 2^22 normals of the seed-1 (B1) and seed-7 (Polar) streams and on a
+    mu != 0 stream: FP64 as the largest ulp distance; FP32, BF16 and FP16 as
+    the largest |dz| / max(1, |z|) and as the largest fraction of the bar.
+    Printed as one line per case (and asserted within the bars)."""
+    n = 1 << 22
+    rows = []
+    for method, seed, mu, sigma in (("b1", 1, 0.0, 1.0), ("polar", 7, 0.0, 1.0),
+                                    ("b1", 5, -3.5, 2.0), ("polar", 5, -3.5, 2.0)):
+        ref, _ = (O.b1 if method == "b1" else O.polar)(seed, 0, n, mu, sigma)
+        for dtype in FLOAT_DTYPES:
+            z = host(run(method, seed, 0, n, dtype, mu, sigma))
+            frac = assert_close(z, ref, dtype, mu, sigma, what="%s %s" % (method, NAME[dtype]))
+            rel = float(np.max(np.abs(z - ref) / np.maximum(1.0, np.abs(ref))))
+            rows.append("%-5s mu=%5.1f sigma=%.1f %-4s max|dz|/max(1,|z|) %.3e  %s" % (
+                method, mu, sigma, NAME[dtype], rel,
+                ("max ulp %d" % frac) if dtype == nb.NRNG_F64 else ("max err/bar %.3f" % frac)))
+    with capsys.disabled():
+        print("\n[error report, n = 2^22 per case]\n" + "\n".join(rows), flush=True)
