@@ -4,7 +4,8 @@ This package wraps ``nrng_oracle.c`` -- a plain single-threaded C99
 implementation, in IEEE double precision without fused multiply-add, of
 Box-Muller Algorithm B1 and the Polar method (Algorithm P) from Section 2 of
 Brent's "Fast Normal Random Number Generators for Vector Processors" (1993),
-fed by a counter-based SplitMix64 uniform stream.
+and method P2 of its Section 4, fed by a counter-based SplitMix64 uniform
+stream.
 
 Only the test suite, the smoke check and the CPU-baseline leg of the
 benchmark may import it.  The product library (``paper_1004_3105_amd``)
@@ -69,6 +70,13 @@ def lib():
                 "orc_polar_count": (u64, [u64, u64, u64]),
                 "orc_polar_trace": (u64, [u64, u64, u64, vp, vp]),
                 "orc_polar_window": (u64, [u64, u64, u64, u64, f64, f64, vp]),
+                "orc_p2_cheb": (None, [ctypes.c_int, vp]),
+                "orc_p2_h": (f64, [ctypes.c_int, f64]),
+                "orc_polar2_accept": (ctypes.c_int, [i32, i32]),
+                "orc_polar2_xy": (u64, [vp, u64, f64, f64, vp, vp]),
+                "orc_polar2": (u64, [u64, u64, u64, f64, f64, vp]),
+                "orc_polar2_count": (u64, [u64, u64, u64]),
+                "orc_polar2_window": (u64, [u64, u64, u64, u64, f64, f64, vp]),
                 "orc_moments": (None, [vp, u64, vp]),
                 "orc_normal_cdf": (f64, [f64]),
                 "orc_ks": (f64, [vp, u64, ctypes.c_int, f64, f64]),
@@ -257,6 +265,50 @@ def polar_parallel(seed: int, offset: int, n: int, mu: float = 0.0, sigma: float
     bits = np.unpackbits(masks.view(np.uint8), bitorder="little")
     jlast = c0 + int(np.flatnonzero(bits)[need - 1])
     return out[:n], 2 * (jlast + 1)
+
+
+# ---------------------------------------------------------------- P2
+def p2_cheb(degree: int = 15) -> np.ndarray:
+    """Chebyshev coefficients c_0..c_degree of h(v) on [-1, 1]."""
+    c = np.empty(degree + 1, dtype=np.float64)
+    lib().orc_p2_cheb(degree, _p(c))
+    return c
+
+
+def p2_h(v: float, degree: int = 15) -> float:
+    """h(v) by the Chebyshev series truncated after T_degree."""
+    return float(lib().orc_p2_h(degree, v))
+
+
+def polar2(seed: int, offset: int, n: int, mu: float = 0.0, sigma: float = 1.0):
+    """n normals by method P2; returns (values, uniforms consumed)."""
+    out = np.empty(max(n, 1), dtype=np.float64)
+    used = lib().orc_polar2(seed & M64, offset & M64, n, mu, sigma, _p(out))
+    return out[:n], int(used)
+
+
+def polar2_xy(xy, mu: float = 0.0, sigma: float = 1.0):
+    """Method P2 on explicit integer candidates; as polar_xy."""
+    xy = np.ascontiguousarray(xy, dtype=np.int32).reshape(-1)
+    ncand = xy.size // 2
+    out = np.empty(max(2 * ncand, 1), dtype=np.float64)
+    masks = np.empty(max((ncand + 63) // 64, 1), dtype=np.uint64)
+    a = int(lib().orc_polar2_xy(_p(xy), ncand, mu, sigma, _p(out), _p(masks)))
+    return out[:2 * a], masks[:(ncand + 63) // 64], a
+
+
+def polar2_accept(X: int, Y: int) -> bool:
+    return bool(lib().orc_polar2_accept(int(X), int(Y)))
+
+
+def polar2_count(seed: int, offset: int, ncand: int) -> int:
+    return int(lib().orc_polar2_count(seed & M64, offset & M64, ncand))
+
+
+def polar2_window(seed: int, offset: int, j0: int, ncand: int, mu: float = 0.0, sigma: float = 1.0):
+    out = np.empty(max(2 * ncand, 1), dtype=np.float64)
+    a = int(lib().orc_polar2_window(seed & M64, offset & M64, j0, ncand, mu, sigma, _p(out)))
+    return out[:2 * a]
 
 
 # ---------------------------------------------------------------- statistics

@@ -1,8 +1,9 @@
 /*
  * nrng_oracle.c -- plain, slow, single-threaded FP64 reference for the
- * normal-deviate path (Box-Muller Algorithm B1 and the Polar method,
- * Algorithm P, of Brent, "Fast Normal Random Number Generators for Vector
- * Processors", 1993).
+ * normal-deviate path: Box-Muller Algorithm B1 and the Polar method,
+ * Algorithm P (Section 2), and method P2 (Section 4, the Polar method with
+ * the radius factor of method B3, Section 3) of Brent, "Fast Normal Random
+ * Number Generators for Vector Processors", 1993.
  *
  * TEST INFRASTRUCTURE ONLY.  Nothing in the product library may include,
  * link or call this file.  It is used by the test suite, by the smoke check
@@ -14,8 +15,9 @@
  * Build: gcc -O2 -std=c99 -ffp-contract=off -fPIC -shared (no fused
  * multiply-add, so every line below is one IEEE-754 double operation).
  *
- * Pins (see the tests): the SplitMix64 check sequence, closed-form B1 and
- * Polar values for chosen inputs, brute-force lattice counts of the Polar
+ * Pins (see the tests): the SplitMix64 check sequence, closed-form B1,
+ * Polar and P2 values for chosen inputs, the paper's error bound of the P2
+ * polynomial against the closed form, brute-force lattice counts of the Polar
  * acceptance predicate on small grids, the pi/4 acceptance rate, the
  * uniformity of the accepted s, sample moments and a Kolmogorov-Smirnov
  * statistic against the normal CDF.
@@ -258,6 +260,187 @@ uint64_t orc_polar_window(uint64_t seed, uint64_t offset, uint64_t j0, uint64_t 
         int32_t Y = orc_int32(seed, offset + 2 * j + 1);
         if (orc_polar_accept(X, Y)) {
             polar_value(X, Y, mu, sigma, &out[2 * a], &out[2 * a + 1]);
+            ++a;
+        }
+    }
+    return a;
+}
+
+/* ------------------------------------------------------------------------
+ * Method P2, Section 4 (with the approximation of Section 3).
+ *
+ * Step 4 of Algorithm P may take -ln of any uniform variable on (0, 1] that
+ * is independent of the angle of (x, y) (Knuth's proof), in particular of
+ * 1 - s.  The radius factor becomes sigma sqrt(2) g(s) with
+ *   g(u) = sqrt(-ln(1 - u) / u),   g(u) = 1 + u/4 + ... near u = 0,
+ * the function of method B3.  For s <= 8/9, g(s) = h(v) with
+ *   v = (6 s - 4) / (4 - 3 s)  (Section 3, rho = 1: [0, 8/9] -> [-1, 1],
+ *   singularities of h at v = +-2),
+ * and h is replaced by its Chebyshev series truncated after T_15 (the
+ * degree-15 polynomial of Section 3, absolute error below 2e-11 on
+ * [-1, 1]).  For s > 8/9 the library ln and sqrt are used.  Outputs are
+ * x r sqrt(2) + mu and y r sqrt(2) + mu.
+ *
+ * Rejection is the literal step 3: s >= 1 only (S >= 2^62).  s = 0 is kept:
+ * g(0) = 1 is finite (v = -1), and the pair (0, 0) yields (mu, mu).
+ * --------------------------------------------------------------------- */
+#define P2_DEGREE 15
+#define P2_NODES 64
+
+/* g(u) for 0 <= u < 1 (log1p keeps -ln(1 - u) accurate for small u). */
+static double p2_g(double u)
+{
+    if (u == 0.0)
+        return 1.0;
+    return sqrt(-log1p(-u) / u);
+}
+
+/* h(v) = g(u) with u the inverse image of v: u = 4 (v + 1) / (6 + 3 v). */
+static double p2_h_exact(double v)
+{
+    return p2_g(4.0 * (v + 1.0) / (6.0 + 3.0 * v));
+}
+
+/* Chebyshev coefficients c[0..degree] of h on [-1, 1], from the discrete
+ * orthogonality of T_k at the P2_NODES Chebyshev points t_j = cos(pi (j +
+ * 1/2) / N): c_k = (2/N) sum_j h(t_j) T_k(t_j), with c_0 halved.  With 64
+ * points the aliased terms are those of degree 113 and above, far below
+ * double precision, so these are the coefficients of the series itself. */
+void orc_p2_cheb(int degree, double *c)
+{
+    double f[P2_NODES], th[P2_NODES];
+    for (int j = 0; j < P2_NODES; ++j) {
+        th[j] = M_PI * ((double)j + 0.5) / (double)P2_NODES;
+        f[j] = p2_h_exact(cos(th[j]));
+    }
+    for (int k = 0; k <= degree; ++k) {
+        double sum = 0.0;
+        for (int j = 0; j < P2_NODES; ++j)
+            sum += f[j] * cos((double)k * th[j]);
+        c[k] = 2.0 * sum / (double)P2_NODES;
+    }
+    c[0] *= 0.5;
+}
+
+/* The truncated series sum_{k <= degree} c_k T_k(v), with T_k by the
+ * three-term recurrence T_{k+1} = 2 v T_k - T_{k-1}. */
+static double cheb_sum(const double *c, int degree, double v)
+{
+    double t0 = 1.0, t1 = v, sum = c[0];
+    if (degree >= 1)
+        sum += c[1] * t1;
+    for (int k = 2; k <= degree; ++k) {
+        double t2 = 2.0 * v * t1 - t0;
+        sum += c[k] * t2;
+        t0 = t1;
+        t1 = t2;
+    }
+    return sum;
+}
+
+/* h(v) by the degree-d truncated series (coefficients recomputed per call:
+ * for the pins only). */
+double orc_p2_h(int degree, double v)
+{
+    double c[P2_DEGREE + 8];
+    if (degree < 0 || degree > P2_DEGREE + 7)
+        return NAN;
+    orc_p2_cheb(degree, c);
+    return cheb_sum(c, degree, v);
+}
+
+int orc_polar2_accept(int32_t X, int32_t Y)
+{
+    uint64_t S = (uint64_t)((int64_t)X * (int64_t)X) + (uint64_t)((int64_t)Y * (int64_t)Y);
+    return S < (1ull << 62);
+}
+
+/* Step 4 and 5 of P2 for an accepted (X, Y); c holds the degree-15
+ * coefficients. */
+static void polar2_value(const double *c, int32_t X, int32_t Y, double mu, double sigma, double *zx,
+                         double *zy)
+{
+    uint64_t S = (uint64_t)((int64_t)X * (int64_t)X) + (uint64_t)((int64_t)Y * (int64_t)Y);
+    double s = (double)S * 0x1p-62;
+    double r;
+    if (s > 8.0 / 9.0) {
+        r = sigma * sqrt(-log(1.0 - s) / s);
+    } else {
+        double v = (6.0 * s - 4.0) / (4.0 - 3.0 * s);
+        r = sigma * cheb_sum(c, P2_DEGREE, v);
+    }
+    double rt = r * M_SQRT2;
+    *zx = rt * ((double)X * 0x1p-31) + mu;
+    *zy = rt * ((double)Y * 0x1p-31) + mu;
+}
+
+/* As orc_polar_xy, for method P2. */
+uint64_t orc_polar2_xy(const int32_t *xy, uint64_t ncand, double mu, double sigma, double *out,
+                       uint64_t *mask_words)
+{
+    double c[P2_DEGREE + 1];
+    orc_p2_cheb(P2_DEGREE, c);
+    uint64_t a = 0;
+    if (mask_words)
+        for (uint64_t w = 0; w < (ncand + 63) / 64; ++w)
+            mask_words[w] = 0;
+    for (uint64_t j = 0; j < ncand; ++j) {
+        int32_t X = xy[2 * j], Y = xy[2 * j + 1];
+        if (!orc_polar2_accept(X, Y))
+            continue;
+        if (mask_words)
+            mask_words[j / 64] |= 1ull << (j % 64);
+        if (out)
+            polar2_value(c, X, Y, mu, sigma, &out[2 * a], &out[2 * a + 1]);
+        ++a;
+    }
+    return a;
+}
+
+/* As orc_polar, for method P2 (same candidates, pairing, order, odd-n rule
+ * and consumed count). */
+uint64_t orc_polar2(uint64_t seed, uint64_t offset, uint64_t n, double mu, double sigma,
+                    double *out)
+{
+    double c[P2_DEGREE + 1];
+    orc_p2_cheb(P2_DEGREE, c);
+    uint64_t written = 0, j = 0;
+    while (written < n) {
+        int32_t X = orc_int32(seed, offset + 2 * j);
+        int32_t Y = orc_int32(seed, offset + 2 * j + 1);
+        if (orc_polar2_accept(X, Y)) {
+            double zx, zy;
+            polar2_value(c, X, Y, mu, sigma, &zx, &zy);
+            out[written++] = zx;
+            if (written < n)
+                out[written++] = zy;
+        }
+        ++j;
+    }
+    return 2 * j;
+}
+
+uint64_t orc_polar2_count(uint64_t seed, uint64_t offset, uint64_t ncand)
+{
+    uint64_t a = 0;
+    for (uint64_t j = 0; j < ncand; ++j)
+        a += (uint64_t)orc_polar2_accept(orc_int32(seed, offset + 2 * j),
+                                         orc_int32(seed, offset + 2 * j + 1));
+    return a;
+}
+
+/* As orc_polar_window, for method P2. */
+uint64_t orc_polar2_window(uint64_t seed, uint64_t offset, uint64_t j0, uint64_t ncand, double mu,
+                           double sigma, double *out)
+{
+    double c[P2_DEGREE + 1];
+    orc_p2_cheb(P2_DEGREE, c);
+    uint64_t a = 0;
+    for (uint64_t j = j0; j < j0 + ncand; ++j) {
+        int32_t X = orc_int32(seed, offset + 2 * j);
+        int32_t Y = orc_int32(seed, offset + 2 * j + 1);
+        if (orc_polar2_accept(X, Y)) {
+            polar2_value(c, X, Y, mu, sigma, &out[2 * a], &out[2 * a + 1]);
             ++a;
         }
     }

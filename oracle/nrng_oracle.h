@@ -31,6 +31,17 @@ uint64_t orc_polar_trace(uint64_t seed, uint64_t offset, uint64_t ncand, uint64_
 uint64_t orc_polar_window(uint64_t seed, uint64_t offset, uint64_t j0, uint64_t ncand, double mu,
                           double sigma, double *out);
 
+void orc_p2_cheb(int degree, double *c);
+double orc_p2_h(int degree, double v);
+int orc_polar2_accept(int32_t X, int32_t Y);
+uint64_t orc_polar2_xy(const int32_t *xy, uint64_t ncand, double mu, double sigma, double *out,
+                       uint64_t *mask_words);
+uint64_t orc_polar2(uint64_t seed, uint64_t offset, uint64_t n, double mu, double sigma,
+                    double *out);
+uint64_t orc_polar2_count(uint64_t seed, uint64_t offset, uint64_t ncand);
+uint64_t orc_polar2_window(uint64_t seed, uint64_t offset, uint64_t j0, uint64_t ncand, double mu,
+                           double sigma, double *out);
+
 void orc_moments(const double *x, uint64_t n, double *out);
 double orc_normal_cdf(double z);
 double orc_ks(double *x, uint64_t n, int kind, double mu, double sigma);

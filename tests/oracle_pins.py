@@ -18,7 +18,13 @@ What pins what:
   * the acceptance rate pi/4, the uniformity of the accepted s and of the
     polar angle, and moments / KS against the normal CDF pin the stream
     composition statistically;
-  * SciPy pins the oracle's statistics routines.
+  * SciPy pins the oracle's statistics routines;
+  * method P2 (Section 4): the paper's error bound of its degree-15
+    polynomial (below 2e-11 on [-1, 1]) against g(s) = sqrt(-ln(1-s)/s)
+    computed here from the closed form, closed-form values on both sides of
+    the split at s = 8/9, the lattice count with the origin accepted, the
+    identity z_P2 = z_P sqrt(ln(1 - s)/ln(s)) pair by pair against the Polar
+    stream, and -ln(1 - s) = (zx^2 + zy^2)/2 being exponential(1).
 """
 from __future__ import annotations
 
@@ -262,6 +268,119 @@ def check_polar_distribution(n: int = 1 << 20):
     assert stats.kstest(e, "expon").statistic < 1.95 / math.sqrt(e.size)
 
 
+# ------------------------------------------------------------------ P2
+def _g_closed(s: np.ndarray) -> np.ndarray:
+    s = np.asarray(s, dtype=np.float64)
+    out = np.ones_like(s)
+    nz = s != 0
+    out[nz] = np.sqrt(-np.log1p(-s[nz]) / s[nz])
+    return out
+
+
+def check_p2_poly_bound():
+    # Section 3: the degree-15 truncation approximates h(v) = g(s) with
+    # absolute error below 2e-11 on [-1, 1], and v = (6s - 4)/(4 - 3s) maps
+    # [0, 8/9] onto [-1, 1]
+    s = np.concatenate([np.linspace(0.0, 8.0 / 9.0, 4001), [1e-12, 1e-6, 0.5, 8.0 / 9.0]])
+    v = (6 * s - 4) / (4 - 3 * s)
+    assert abs(v[0] + 1) == 0 and abs(v[4000] - 1) < 1e-15
+    h = np.array([O.p2_h(float(x)) for x in v])
+    err = np.abs(h - _g_closed(s))
+    assert err.max() < 2e-11, err.max()
+    # g(u) = 1 + u/4 + ... near 0
+    d = (O.p2_h(float((6 * 1e-4 - 4) / (4 - 3e-4))) - 1.0) / 1e-4
+    assert abs(d - 0.25) < 1e-4, d
+    # the coefficients decay like those of a function analytic inside the
+    # ellipse through the singularities at v = +-2 (rate 2 - sqrt(3))
+    c = O.p2_cheb(15)
+    assert c[0] > 1.0 and np.all(np.abs(c[12:]) < 1e-8) and np.all(np.abs(c[4:]) < 1e-3)
+
+
+def check_polar2_hand():
+    rows = golden_rows("polar2_hand_values.txt")
+    xy = np.array([[int(r[0]), int(r[1])] for r in rows], dtype=np.int64).astype(np.int32)
+    out, masks, a = O.polar2_xy(xy)
+    acc = [int(r[2]) for r in rows]
+    assert a == sum(acc)
+    bits = [(int(masks[j // 64]) >> (j % 64)) & 1 for j in range(len(rows))]
+    assert bits == acc, (bits, acc)
+    vals = out.reshape(-1, 2)
+    k = 0
+    for r in rows:
+        if r[2] == "0":
+            assert not O.polar2_accept(int(r[0]), int(r[1]))
+            continue
+        kind, amt = r[5].split(":")
+        for c in range(2):
+            want = closed_form(r[3 + c])
+            got = vals[k, c]
+            if kind == "abs" or want == 0.0:
+                assert abs(got - want) <= float(amt), (r, c, got, want)
+            else:
+                assert ulp_dist64([got], [want])[0] <= int(amt), (r, c, got, want)
+        k += 1
+    out2, _, _ = O.polar2_xy(xy, mu=2.0, sigma=3.0)
+    assert np.allclose(out2, 2.0 + 3.0 * out, rtol=0, atol=1e-13)
+
+
+def check_polar2_lattice(bmax: int = 9):
+    # P2 rejects only s >= 1, so its lattice count is Algorithm P's plus the origin
+    for b in range(1, bmax + 1):
+        h = 1 << (b - 1)
+        g = np.arange(-h, h, dtype=np.int64)
+        X, Y = np.meshgrid(g, g, indexing="ij")
+        shift = 32 - b
+        xy = np.stack([X.ravel() << shift, Y.ravel() << shift], axis=1).astype(np.int32)
+        _, _, a = O.polar2_xy(xy)
+        assert a == lattice_count(b) + 1, (b, a)
+    R = 1 << 31
+    for (x, y, acc) in [(-R, 0, 0), (0, -R, 0), (-R, -R, 0), (R - 1, 0, 1), (0, 0, 1), (1, 0, 1)]:
+        assert O.polar2_accept(x, y) == bool(acc), (x, y)
+
+
+def check_polar2_vs_polar():
+    # same candidates, pairing, order and consumed count as Algorithm P (no
+    # (0, 0) candidate occurs in these streams); pair by pair,
+    # z_P2 = z_P sqrt(ln(1 - s) / ln(s)), with s from the stream's integers
+    seed, off, n = 7, 12, 20001
+    z2, used2 = O.polar2(seed, off, n)
+    z1, used1 = O.polar(seed, off, n)
+    assert used1 == used2
+    xy = O.int32s(seed, off, used2).astype(np.int64).reshape(-1, 2)
+    S = xy[:, 0] ** 2 + xy[:, 1] ** 2
+    keep = (S > 0) & (S < (1 << 62))
+    s = S[keep].astype(np.float64) * 2.0**-62
+    ratio = np.sqrt(np.log1p(-s) / np.log(s))
+    k = (n + 1) // 2
+    want = (z1.reshape(-1) if n % 2 == 0 else np.append(z1, 0.0)).reshape(-1, 2) * ratio[:k, None]
+    got = (z2 if n % 2 == 0 else np.append(z2, 0.0)).reshape(-1, 2)
+    assert np.allclose(got, want, rtol=5e-10, atol=5e-10)
+    # composition, as for Algorithm P: explicit candidates, windows, restarts
+    ref, masks, a = O.polar2_xy(O.int32s(seed, off, used2))
+    assert a == k and np.array_equal(z2, ref[:n])
+    assert O.polar2_count(seed, off, used2 // 2) == a
+    j0 = 1000
+    w = O.polar2_window(seed, off, j0, 3000)
+    before = O.polar2_count(seed, off, j0)
+    assert np.array_equal(w, ref[2 * before: 2 * before + w.size])
+    za, ua = O.polar2(seed, off, 1000)
+    zb, ub = O.polar2(seed, off + ua, n - 1000)
+    assert np.array_equal(np.concatenate([za, zb]), z2) and ua + ub == used2
+    zs, _ = O.polar2(seed, off, n, mu=1.5, sigma=0.5)
+    assert np.allclose(zs, 1.5 + 0.5 * z2, rtol=0, atol=1e-14)
+
+
+def check_polar2_distribution(n: int = 1 << 20):
+    z, _ = O.polar2(7, 0, n)
+    _dist_checks(z)
+    from scipy import stats
+    ang = (np.arctan2(z[1::2], z[0::2]) / (2 * math.pi)) % 1.0
+    assert stats.kstest(ang, "uniform").statistic < 1.95 / math.sqrt(ang.size)
+    # (zx^2 + zy^2)/2 = -ln(1 - s), exponential(1) because 1 - s is uniform
+    e = 0.5 * (z[0::2] ** 2 + z[1::2] ** 2)
+    assert stats.kstest(e, "expon").statistic < 1.95 / math.sqrt(e.size)
+
+
 def check_stats_routines():
     from scipy import special, stats
     g = np.random.Generator(np.random.PCG64(5))
@@ -290,5 +409,6 @@ ALL_CHECKS = [
     check_splitmix_published, check_stream_definitions, check_b1_hand, check_b1_words_definition,
     check_b1_composition, check_polar_hand, check_polar_lattice, check_polar_composition,
     check_polar_accept_rate, check_polar_s_uniform, check_b1_distribution, check_polar_distribution,
-    check_stats_routines,
+    check_stats_routines, check_p2_poly_bound, check_polar2_hand, check_polar2_lattice, check_polar2_vs_polar,
+    check_polar2_distribution,
 ]

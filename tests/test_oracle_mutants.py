@@ -49,6 +49,24 @@ MUTANTS = {
     "polar_odd": ("if (written < n)\n                out[written++] = zy;", "out[written++] = zy;"),
     "polar_trace_prefix": ("word_prefix[w] = a;", "word_prefix[w] = a + 1;"),
     "polar_window_start": ("for (uint64_t j = j0; j < j0 + ncand; ++j) {", "for (uint64_t j = j0 + 1; j < j0 + ncand; ++j) {"),
+    "p2_degree": ("#define P2_DEGREE 15", "#define P2_DEGREE 14"),
+    "p2_nodes": ("#define P2_NODES 64", "#define P2_NODES 12"),
+    "p2_map": ("double v = (6.0 * s - 4.0) / (4.0 - 3.0 * s);", "double v = (6.0 * s - 4.0) / (4.0 + 3.0 * s);"),
+    "p2_inverse_map": ("p2_g(4.0 * (v + 1.0) / (6.0 + 3.0 * v))", "p2_g(4.0 * (v + 1.0) / (6.0 - 3.0 * v))"),
+    "p2_g_sign": ("return sqrt(-log1p(-u) / u);", "return sqrt(log1p(u) / u);"),
+    "p2_threshold": ("if (s > 8.0 / 9.0) {", "if (s > 0.97) {"),
+    "p2_lib_ln_s": ("r = sigma * sqrt(-log(1.0 - s) / s);", "r = sigma * sqrt(-log(s) / s);"),
+    "p2_lib_drop_div": ("r = sigma * sqrt(-log(1.0 - s) / s);", "r = sigma * sqrt(-log(1.0 - s));"),
+    "p2_sqrt2": ("double rt = r * M_SQRT2;", "double rt = r;"),
+    "p2_swap_xy": ("*zx = rt * ((double)X * 0x1p-31) + mu;\n    *zy = rt * ((double)Y * 0x1p-31) + mu;",
+                   "*zx = rt * ((double)Y * 0x1p-31) + mu;\n    *zy = rt * ((double)X * 0x1p-31) + mu;"),
+    "p2_accept_zero": ("    return S < (1ull << 62);\n}", "    return S != 0 && S < (1ull << 62);\n}"),
+    "p2_cheb_c0": ("    c[0] *= 0.5;\n}", "}"),
+    "p2_recurrence": ("double t2 = 2.0 * v * t1 - t0;", "double t2 = 2.0 * v * t1 + t0;"),
+    "p2_node_phase": ("th[j] = M_PI * ((double)j + 0.5) / (double)P2_NODES;", "th[j] = M_PI * (double)j / (double)P2_NODES;"),
+    "p2_consumed": ("            polar2_value(c, X, Y, mu, sigma, &zx, &zy);\n            out[written++] = zx;\n            if (written < n)\n                out[written++] = zy;\n        }\n        ++j;\n    }\n    return 2 * j;",
+                    "            polar2_value(c, X, Y, mu, sigma, &zx, &zy);\n            out[written++] = zx;\n            if (written < n)\n                out[written++] = zy;\n        }\n        ++j;\n    }\n    return 2 * j + 2;"),
+    "p2_sigma": ("r = sigma * cheb_sum(c, P2_DEGREE, v);", "r = cheb_sum(c, P2_DEGREE, v);"),
     "kurtosis": ("out[3] = m4 / (m2 * m2);", "out[3] = m4 / m2;"),
     "skew": ("out[2] = m3 / (m2 * sqrt(m2));", "out[2] = m3 / m2;"),
     "ks_step": ("double hi = (double)(i + 1) / (double)n - f;", "double hi = (double)i / (double)n - f;"),
