@@ -287,39 +287,45 @@ uint64_t orc_polar_window(uint64_t seed, uint64_t offset, uint64_t j0, uint64_t 
 #define P2_DEGREE 15
 #define P2_NODES 64
 
-/* g(u) for 0 <= u < 1 (log1p keeps -ln(1 - u) accurate for small u). */
-static double p2_g(double u)
+/* g(u) for 0 <= u < 1 (log1p keeps -ln(1 - u) accurate for small u), in
+ * the extended precision of long double: only the coefficients below are
+ * computed from it. */
+static long double p2_g(long double u)
 {
-    if (u == 0.0)
-        return 1.0;
-    return sqrt(-log1p(-u) / u);
+    if (u == 0.0L)
+        return 1.0L;
+    return sqrtl(-log1pl(-u) / u);
 }
 
 /* h(v) = g(u) with u the inverse image of v: u = 4 (v + 1) / (6 + 3 v). */
-static double p2_h_exact(double v)
+static long double p2_h_exact(long double v)
 {
-    return p2_g(4.0 * (v + 1.0) / (6.0 + 3.0 * v));
+    return p2_g(4.0L * (v + 1.0L) / (6.0L + 3.0L * v));
 }
 
 /* Chebyshev coefficients c[0..degree] of h on [-1, 1], from the discrete
  * orthogonality of T_k at the P2_NODES Chebyshev points t_j = cos(pi (j +
  * 1/2) / N): c_k = (2/N) sum_j h(t_j) T_k(t_j), with c_0 halved.  With 64
  * points the aliased terms are those of degree 113 and above, far below
- * double precision, so these are the coefficients of the series itself. */
+ * double precision, so these are the coefficients of the series itself.
+ * The sums run in long double so that each coefficient is the series'
+ * coefficient rounded to double (in double the 64-term sums would leave
+ * errors near 1e-15 in each). */
 void orc_p2_cheb(int degree, double *c)
 {
-    double f[P2_NODES], th[P2_NODES];
+    long double f[P2_NODES], th[P2_NODES];
+    const long double pi = 3.141592653589793238462643383279502884L;
     for (int j = 0; j < P2_NODES; ++j) {
-        th[j] = M_PI * ((double)j + 0.5) / (double)P2_NODES;
-        f[j] = p2_h_exact(cos(th[j]));
+        th[j] = pi * ((long double)j + 0.5L) / (long double)P2_NODES;
+        f[j] = p2_h_exact(cosl(th[j]));
     }
     for (int k = 0; k <= degree; ++k) {
-        double sum = 0.0;
+        long double sum = 0.0L;
         for (int j = 0; j < P2_NODES; ++j)
-            sum += f[j] * cos((double)k * th[j]);
-        c[k] = 2.0 * sum / (double)P2_NODES;
+            sum += f[j] * cosl((long double)k * th[j]);
+        long double ck = 2.0L * sum / (long double)P2_NODES;
+        c[k] = (double)(k == 0 ? 0.5L * ck : ck);
     }
-    c[0] *= 0.5;
 }
 
 /* The truncated series sum_{k <= degree} c_k T_k(v), with T_k by the

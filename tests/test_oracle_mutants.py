@@ -52,8 +52,8 @@ MUTANTS = {
     "p2_degree": ("#define P2_DEGREE 15", "#define P2_DEGREE 14"),
     "p2_nodes": ("#define P2_NODES 64", "#define P2_NODES 12"),
     "p2_map": ("double v = (6.0 * s - 4.0) / (4.0 - 3.0 * s);", "double v = (6.0 * s - 4.0) / (4.0 + 3.0 * s);"),
-    "p2_inverse_map": ("p2_g(4.0 * (v + 1.0) / (6.0 + 3.0 * v))", "p2_g(4.0 * (v + 1.0) / (6.0 - 3.0 * v))"),
-    "p2_g_sign": ("return sqrt(-log1p(-u) / u);", "return sqrt(log1p(u) / u);"),
+    "p2_inverse_map": ("p2_g(4.0L * (v + 1.0L) / (6.0L + 3.0L * v))", "p2_g(4.0L * (v + 1.0L) / (6.0L - 3.0L * v))"),
+    "p2_g_sign": ("return sqrtl(-log1pl(-u) / u);", "return sqrtl(log1pl(u) / u);"),
     "p2_threshold": ("if (s > 8.0 / 9.0) {", "if (s > 0.97) {"),
     "p2_lib_ln_s": ("r = sigma * sqrt(-log(1.0 - s) / s);", "r = sigma * sqrt(-log(s) / s);"),
     "p2_lib_drop_div": ("r = sigma * sqrt(-log(1.0 - s) / s);", "r = sigma * sqrt(-log(1.0 - s));"),
@@ -61,9 +61,9 @@ MUTANTS = {
     "p2_swap_xy": ("*zx = rt * ((double)X * 0x1p-31) + mu;\n    *zy = rt * ((double)Y * 0x1p-31) + mu;",
                    "*zx = rt * ((double)Y * 0x1p-31) + mu;\n    *zy = rt * ((double)X * 0x1p-31) + mu;"),
     "p2_accept_zero": ("    return S < (1ull << 62);\n}", "    return S != 0 && S < (1ull << 62);\n}"),
-    "p2_cheb_c0": ("    c[0] *= 0.5;\n}", "}"),
+    "p2_cheb_c0": ("c[k] = (double)(k == 0 ? 0.5L * ck : ck);", "c[k] = (double)ck;"),
     "p2_recurrence": ("double t2 = 2.0 * v * t1 - t0;", "double t2 = 2.0 * v * t1 + t0;"),
-    "p2_node_phase": ("th[j] = M_PI * ((double)j + 0.5) / (double)P2_NODES;", "th[j] = M_PI * (double)j / (double)P2_NODES;"),
+    "p2_node_phase": ("th[j] = pi * ((long double)j + 0.5L) / (long double)P2_NODES;", "th[j] = pi * (long double)j / (long double)P2_NODES;"),
     "p2_consumed": ("            polar2_value(c, X, Y, mu, sigma, &zx, &zy);\n            out[written++] = zx;\n            if (written < n)\n                out[written++] = zy;\n        }\n        ++j;\n    }\n    return 2 * j;",
                     "            polar2_value(c, X, Y, mu, sigma, &zx, &zy);\n            out[written++] = zx;\n            if (written < n)\n                out[written++] = zy;\n        }\n        ++j;\n    }\n    return 2 * j + 2;"),
     "p2_sigma": ("r = sigma * cheb_sum(c, P2_DEGREE, v);", "r = cheb_sum(c, P2_DEGREE, v);"),
