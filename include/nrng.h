@@ -4,7 +4,8 @@
  *
  * The library turns a counter-based stream of uniform deviates into
  * N(mu, sigma^2) deviates by the two methods of Section 2 of R. P. Brent,
- * "Fast Normal Random Number Generators for Vector Processors" (1993):
+ * "Fast Normal Random Number Generators for Vector Processors" (1993), and
+ * by the paper's method P2 (Section 4, see nrng_polar2):
  *
  *   Algorithm B1 (Box-Muller):  r = sigma sqrt(-2 ln(1 - u)),
  *                               x = r sin(2 pi v) + mu,  y = r cos(2 pi v) + mu;
@@ -67,7 +68,7 @@ extern "C" {
 enum nrng_dtype { NRNG_F64 = 0, NRNG_F32 = 1, NRNG_BF16 = 2, NRNG_F16 = 3 };
 
 /* Methods for nrng_batched. */
-enum nrng_method { NRNG_METHOD_B1 = 0, NRNG_METHOD_POLAR = 1 };
+enum nrng_method { NRNG_METHOD_B1 = 0, NRNG_METHOD_POLAR = 1, NRNG_METHOD_P2 = 2 };
 
 /* Status codes. */
 enum nrng_status {
@@ -129,6 +130,25 @@ int nrng_boxmuller(uint64_t seed, uint64_t offset, uint64_t n, double mu, double
 int nrng_polar(uint64_t seed, uint64_t offset, uint64_t n, double mu, double sigma, void *out,
                int dtype, void *stream, uint64_t *d_consumed);
 
+/* ------------------------------------------------------------------------
+ * Method P2 (Section 4), over one stream: the Polar method with step 4
+ * taking -ln(1 - s) in place of -ln(s) (1 - s is also uniform and
+ * independent of the angle of (x, y)), so the radius factor is
+ * sigma sqrt(2) g(s) with g(s) = sqrt(-ln(1 - s) / s), the function of
+ * method B3 (Section 3).  For s <= 8/9, g is a polynomial in
+ * v = (6 s - 4) / (4 - 3 s) (the Section 3 change of variable with rho = 1),
+ * the truncated Chebyshev series of degree 15 in FP64 and degree 9 in FP32
+ * (truncation errors 1.5e-11 and 6e-8); for s > 8/9, logarithm and square
+ * root.  Outputs x r sqrt(2) + mu and y r sqrt(2) + mu.
+ *   Candidates, pairing, stable order, odd-n rule, offsets and the consumed
+ *   count are those of nrng_polar, except that step 3 rejects only s >= 1:
+ *   the candidate (0, 0) (s = 0, g(0) = 1) is accepted and gives (mu, mu).
+ *   The values differ from nrng_polar's (a different transform of the same
+ *   candidates).  Same arguments, errors and workspace as nrng_polar; the
+ *   launch configuration is the Polar one (nrng_tune_set kernel 1). */
+int nrng_polar2(uint64_t seed, uint64_t offset, uint64_t n, double mu, double sigma, void *out,
+                int dtype, void *stream, uint64_t *d_consumed);
+
 /* Polar method with a device-resident counter offset, for repeated fills
  * captured in a HIP graph: reads the offset from *d_cursor when the kernel
  * runs and advances *d_cursor by the number of uniforms consumed, so that
@@ -143,7 +163,7 @@ int nrng_polar_dev(uint64_t seed, uint64_t *d_cursor, uint64_t n, double mu, dou
  * Many independent streams in one launch sequence: one small set-up kernel
  * builds the tile table on the device, then one persistent B1 kernel, or
  * the three Polar kernels, cover every stream.
- *   method       NRNG_METHOD_B1 or NRNG_METHOD_POLAR
+ *   method       NRNG_METHOD_B1, NRNG_METHOD_POLAR or NRNG_METHOD_P2
  *   nstreams     number of streams (0 is a no-op)
  *   d_seed[j], d_offset[j], d_n[j]  stream j's seed, first counter, length
  *   d_out_off[j] element offset of stream j's output in `out`; NULL means
@@ -153,7 +173,7 @@ int nrng_polar_dev(uint64_t seed, uint64_t *d_cursor, uint64_t n, double mu, dou
  *                range [out_off, out_off + n) does not fit are skipped
  *   d_consumed   optional (may be NULL): d_consumed[j] receives stream j's
  *                consumed uniforms, or UINT64_MAX if the stream was skipped.
- * Stream j's values equal those of nrng_boxmuller / nrng_polar called alone
+ * Stream j's values equal those of nrng_boxmuller / nrng_polar / nrng_polar2 called alone
  * with (d_seed[j], d_offset[j], d_n[j], d_mu[j], d_sigma[j]), bit for bit.
  * The total of d_n over valid streams must not exceed out_len; otherwise the
  * device-side check fails the whole call (every d_consumed[j] = UINT64_MAX,
@@ -174,8 +194,8 @@ int nrng_batched(int method, uint32_t nstreams, const uint64_t *d_seed, const ui
  * next plan or batched call on the device.  nrng_batched(...) is
  * plan + exec.
  * nrng_batched_exec_part runs one half of exec's launch sequence, for timing
- * and profiling the kernels separately: part 1 = the Polar mask and scan
- * kernels (nothing for B1), part 2 = the Polar generate kernel (the B1
+ * and profiling the kernels separately: part 1 = the Polar (or P2) mask and
+ * scan kernels (nothing for B1), part 2 = the generate kernel (the B1
  * kernel for B1), part 0 = both (identical to nrng_batched_exec).  Part 2
  * reads what part 1 of the same plan left in the workspace, so it must
  * follow it on the same stream with no other Polar call in between.  Same
@@ -223,6 +243,7 @@ int nrng_tune_variants(int kernel, uint32_t *pairs, int max_pairs);
  *   candidates are written compactly in order to out (capacity 2 ncand);
  *   d_mask_words (ceil(ncand/64) words, bit j%64 of word j/64 = accept) and
  *   *d_count (number accepted) are written.
+ * nrng_test_polar2_xy: the same for method P2 (accepts 0 <= S < 2^62).
  * nrng_polar_trace: the accept masks and, per 64-candidate word, the output
  *   pair index of its first candidate (exclusive prefix), for candidates
  *   [0, ncand) of stream (seed, offset), produced by the production Polar
@@ -236,6 +257,8 @@ int nrng_test_b1_words(const uint64_t *d_words, uint64_t npairs, double mu, doub
                        void *stream);
 int nrng_test_polar_xy(const int32_t *d_xy, uint64_t ncand, double mu, double sigma, void *out, int dtype,
                        uint64_t *d_mask_words, uint64_t *d_count, void *stream);
+int nrng_test_polar2_xy(const int32_t *d_xy, uint64_t ncand, double mu, double sigma, void *out, int dtype,
+                        uint64_t *d_mask_words, uint64_t *d_count, void *stream);
 int nrng_polar_trace(uint64_t seed, uint64_t offset, uint64_t ncand, uint64_t *d_mask_words,
                      uint64_t *d_word_prefix, void *stream);
 int nrng_test_polar_budget(uint64_t seed, uint64_t offset, uint64_t n, double mu, double sigma, void *out,

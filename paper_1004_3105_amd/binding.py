@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libnrng.so")
 
 NRNG_F64, NRNG_F32, NRNG_BF16, NRNG_F16 = 0, 1, 2, 3
-NRNG_METHOD_B1, NRNG_METHOD_POLAR = 0, 1
+NRNG_METHOD_B1, NRNG_METHOD_POLAR, NRNG_METHOD_P2 = 0, 1, 2
 NRNG_OK, NRNG_EINVAL, NRNG_EDTYPE, NRNG_ERANGE = 0, -1, -2, -3
 NRNG_EHIP, NRNG_ENODEV, NRNG_ECAPTURE, NRNG_ENOMEM = -4, -5, -6, -7
 KERNEL_B1, KERNEL_POLAR, KERNEL_B1_BATCHED = 0, 1, 2
@@ -33,6 +33,7 @@ _SIGS = {
     "nrng_reserve": (_i32, [_u64, _u32]),
     "nrng_boxmuller": (_i32, [_u64, _u64, _u64, _f64, _f64, _vp, _i32, _vp]),
     "nrng_polar": (_i32, [_u64, _u64, _u64, _f64, _f64, _vp, _i32, _vp, _vp]),
+    "nrng_polar2": (_i32, [_u64, _u64, _u64, _f64, _f64, _vp, _i32, _vp, _vp]),
     "nrng_polar_dev": (_i32, [_u64, _vp, _u64, _f64, _f64, _vp, _i32, _vp]),
     "nrng_batched": (_i32, [_i32, _u32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _u64, _i32, _vp, _vp]),
     "nrng_batched_plan": (_i32, [_i32, _u32, _vp, _vp, _u64, _i32, _vp, _vp]),
@@ -46,6 +47,7 @@ _SIGS = {
     "nrng_tune_variants": (_i32, [_i32, ctypes.POINTER(_u32), _i32]),
     "nrng_test_b1_words": (_i32, [_vp, _u64, _f64, _f64, _vp, _i32, _vp]),
     "nrng_test_polar_xy": (_i32, [_vp, _u64, _f64, _f64, _vp, _i32, _vp, _vp, _vp]),
+    "nrng_test_polar2_xy": (_i32, [_vp, _u64, _f64, _f64, _vp, _i32, _vp, _vp, _vp]),
     "nrng_polar_trace": (_i32, [_u64, _u64, _u64, _vp, _vp, _vp]),
     "nrng_test_polar_budget": (_i32, [_u64, _u64, _u64, _f64, _f64, _vp, _i32, _u32, _vp, _vp]),
     "nrng_probe_store": (_i32, [_vp, _u64, _vp]),
@@ -154,6 +156,13 @@ def nrng_polar(seed, offset, n, mu, sigma, out, dtype, stream=None, d_consumed=N
                                           dtype, _stream(stream), _ptr(d_consumed)))
 
 
+def nrng_polar2(seed, offset, n, mu, sigma, out, dtype, stream=None, d_consumed=None) -> None:
+    _need(out, n * _ESIZE.get(dtype, 0), "nrng_polar2 out")
+    _need(d_consumed, 8, "nrng_polar2 d_consumed")
+    _check("nrng_polar2", lib().nrng_polar2(seed & (2**64 - 1), offset & (2**64 - 1), n, mu, sigma, _ptr(out),
+                                            dtype, _stream(stream), _ptr(d_consumed)))
+
+
 def nrng_polar_dev(seed, d_cursor, n, mu, sigma, out, dtype, stream=None) -> None:
     _need(out, n * _ESIZE.get(dtype, 0), "nrng_polar_dev out")
     _need(d_cursor, 8, "nrng_polar_dev d_cursor")
@@ -250,6 +259,15 @@ def nrng_test_polar_xy(d_xy, ncand, mu, sigma, out, dtype, d_mask_words, d_count
     _need(d_count, 8, "nrng_test_polar_xy d_count")
     _check("nrng_test_polar_xy", lib().nrng_test_polar_xy(_ptr(d_xy), ncand, mu, sigma, _ptr(out), dtype,
                                                           _ptr(d_mask_words), _ptr(d_count), _stream(stream)))
+
+
+def nrng_test_polar2_xy(d_xy, ncand, mu, sigma, out, dtype, d_mask_words, d_count, stream=None) -> None:
+    _need(d_xy, 8 * ncand, "nrng_test_polar2_xy d_xy")
+    _need(out, 2 * ncand * _ESIZE.get(dtype, 0), "nrng_test_polar2_xy out")
+    _need(d_mask_words, 8 * ((ncand + 63) // 64), "nrng_test_polar2_xy d_mask_words")
+    _need(d_count, 8, "nrng_test_polar2_xy d_count")
+    _check("nrng_test_polar2_xy", lib().nrng_test_polar2_xy(_ptr(d_xy), ncand, mu, sigma, _ptr(out), dtype,
+                                                            _ptr(d_mask_words), _ptr(d_count), _stream(stream)))
 
 
 def nrng_polar_trace(seed, offset, ncand, d_mask_words, d_word_prefix, stream=None) -> None:

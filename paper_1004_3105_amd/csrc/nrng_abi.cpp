@@ -33,8 +33,8 @@ struct DevState {
     uint64_t *stream_words = nullptr;
     uint64_t *packed_off = nullptr;
     uint64_t stream_cap = 0;
-    int occ_polar[4][4][8] = {};     // generate kernel: [mode][dtype][variant], 0 = not queried
-    int occ_mask[4][8] = {};         // mask kernel: [mode][variant]
+    int occ_polar[2][4][4][8] = {};  // generate kernel: [value method][mode][dtype][variant], 0 = not queried
+    int occ_mask[2][4][8] = {};      // mask kernel: [value method][mode][variant]
     int occ_b1[2][4][8] = {};        // [batched][dtype][variant]
     // the tile table currently in the workspace (from nrng_batched_plan)
     int plan_method = -1, plan_dtype = -1, plan_vi = -1;
@@ -160,24 +160,24 @@ int ensure_streams(DevState &d, uint64_t nstreams, hipStream_t s)
     return NRNG_OK;
 }
 
-int polar_blocks_per_cu(DevState &d, int mode, int dtype, int vi)
+int polar_blocks_per_cu(DevState &d, int mode, int vm, int dtype, int vi)
 {
-    int &o = d.occ_polar[mode][dtype][vi];
+    int &o = d.occ_polar[vm][mode][dtype][vi];
     if (o == 0) {
         int b = 0;
-        if (occupancy_polar(mode, dtype, vi, &b) != (int)hipSuccess || b <= 0)
+        if (occupancy_polar(mode, vm, dtype, vi, &b) != (int)hipSuccess || b <= 0)
             b = 1;
         o = b;
     }
     return o;
 }
 
-int polar_mask_blocks_per_cu(DevState &d, int mode, int vi)
+int polar_mask_blocks_per_cu(DevState &d, int mode, int vm, int vi)
 {
-    int &o = d.occ_mask[mode][vi];
+    int &o = d.occ_mask[vm][mode][vi];
     if (o == 0) {
         int b = 0;
-        if (occupancy_polar_mask(mode, vi, &b) != (int)hipSuccess || b <= 0)
+        if (occupancy_polar_mask(mode, vm, vi, &b) != (int)hipSuccess || b <= 0)
             b = 1;
         o = b;
     }
@@ -257,10 +257,19 @@ PolarArgs polar_args(DevState &d)
     return a;
 }
 
-// Single-stream Polar (also the device-cursor form): `words` is the
-// candidate budget, normally polar_budget_words of the pair count.
-int polar_common(uint64_t seed, uint64_t offset, uint64_t *cursor, uint64_t n, double mu, double sigma, void *out,
-                 int dtype, hipStream_t s, uint64_t *d_consumed, uint64_t force_words)
+// Value method of a batched method id (Polar kernels only).
+int method_vm(int method) { return method == NRNG_METHOD_P2 ? 1 : 0; }
+
+bool method_ok(int method)
+{
+    return method == NRNG_METHOD_B1 || method == NRNG_METHOD_POLAR || method == NRNG_METHOD_P2;
+}
+
+// Single-stream Polar or P2 (also the device-cursor form): `words` is the
+// candidate budget, normally polar_budget_words of the pair count (P2
+// accepts at the same rate, pi/4 plus the measure-zero point s = 0).
+int polar_common(int vm, uint64_t seed, uint64_t offset, uint64_t *cursor, uint64_t n, double mu, double sigma,
+                 void *out, int dtype, hipStream_t s, uint64_t *d_consumed, uint64_t force_words)
 {
     if (!dtype_ok(dtype))
         return NRNG_EDTYPE;
@@ -295,15 +304,15 @@ int polar_common(uint64_t seed, uint64_t offset, uint64_t *cursor, uint64_t n, d
     a.out = out;
     a.consumed = d_consumed;
     const uint64_t chunks = (tiles + kChunkTiles - 1) / kChunkTiles;
-    const uint32_t gm = persistent_grid(*d, polar_mask_blocks_per_cu(*d, MODE_SINGLE, tu.vi), 0, chunks);
+    const uint32_t gm = persistent_grid(*d, polar_mask_blocks_per_cu(*d, MODE_SINGLE, vm, tu.vi), 0, chunks);
     const uint64_t nw = polar_gen_waves(tu.vi);
-    const uint32_t gg = persistent_grid(*d, polar_blocks_per_cu(*d, MODE_SINGLE, dtype, tu.vi), tu.grid_per_cu,
+    const uint32_t gg = persistent_grid(*d, polar_blocks_per_cu(*d, MODE_SINGLE, vm, dtype, tu.vi), tu.grid_per_cu,
                                         (tiles + nw - 1) / nw);
-    return hip_status(launch_polar(MODE_SINGLE, dtype, tu.vi, a, gm, gg, s));
+    return hip_status(launch_polar(MODE_SINGLE, vm, dtype, tu.vi, a, gm, gg, s));
 }
 
 // Trace and explicit-candidate hooks: masks go to the caller's buffer.
-int polar_hook(int mode, uint64_t seed, uint64_t offset, uint64_t ncand, const int32_t *xy, double mu,
+int polar_hook(int mode, int vm, uint64_t seed, uint64_t offset, uint64_t ncand, const int32_t *xy, double mu,
                double sigma, void *out, int dtype, uint64_t *masks, uint64_t *word_prefix, uint64_t *count,
                hipStream_t s)
 {
@@ -332,11 +341,11 @@ int polar_hook(int mode, uint64_t seed, uint64_t offset, uint64_t ncand, const i
     a.xy = xy;
     a.count_out = count;
     const uint64_t chunks = (tiles + kChunkTiles - 1) / kChunkTiles;
-    const uint32_t gm = persistent_grid(*d, polar_mask_blocks_per_cu(*d, mode, tu.vi), 0, chunks);
+    const uint32_t gm = persistent_grid(*d, polar_mask_blocks_per_cu(*d, mode, vm, tu.vi), 0, chunks);
     const uint64_t nw = polar_gen_waves(tu.vi);
     const uint32_t gg =
-        persistent_grid(*d, polar_blocks_per_cu(*d, mode, dtype, tu.vi), tu.grid_per_cu, (tiles + nw - 1) / nw);
-    return hip_status(launch_polar(mode, dtype, tu.vi, a, gm, gg, s));
+        persistent_grid(*d, polar_blocks_per_cu(*d, mode, vm, dtype, tu.vi), tu.grid_per_cu, (tiles + nw - 1) / nw);
+    return hip_status(launch_polar(mode, vm, dtype, tu.vi, a, gm, gg, s));
 }
 
 }  // namespace
@@ -448,7 +457,13 @@ int nrng_boxmuller(uint64_t seed, uint64_t offset, uint64_t n, double mu, double
 int nrng_polar(uint64_t seed, uint64_t offset, uint64_t n, double mu, double sigma, void *out, int dtype,
                void *stream, uint64_t *d_consumed)
 {
-    return polar_common(seed, offset, nullptr, n, mu, sigma, out, dtype, S(stream), d_consumed, 0);
+    return polar_common(0, seed, offset, nullptr, n, mu, sigma, out, dtype, S(stream), d_consumed, 0);
+}
+
+int nrng_polar2(uint64_t seed, uint64_t offset, uint64_t n, double mu, double sigma, void *out, int dtype,
+                void *stream, uint64_t *d_consumed)
+{
+    return polar_common(1, seed, offset, nullptr, n, mu, sigma, out, dtype, S(stream), d_consumed, 0);
 }
 
 int nrng_polar_dev(uint64_t seed, uint64_t *d_cursor, uint64_t n, double mu, double sigma, void *out, int dtype,
@@ -456,7 +471,7 @@ int nrng_polar_dev(uint64_t seed, uint64_t *d_cursor, uint64_t n, double mu, dou
 {
     if (!d_cursor)
         return NRNG_EINVAL;
-    return polar_common(seed, 0, d_cursor, n, mu, sigma, out, dtype, S(stream), nullptr, 0);
+    return polar_common(0, seed, 0, d_cursor, n, mu, sigma, out, dtype, S(stream), nullptr, 0);
 }
 
 int nrng_test_polar_budget(uint64_t seed, uint64_t offset, uint64_t n, double mu, double sigma, void *out,
@@ -464,7 +479,7 @@ int nrng_test_polar_budget(uint64_t seed, uint64_t offset, uint64_t n, double mu
 {
     if (words == 0)
         return NRNG_EINVAL;
-    return polar_common(seed, offset, nullptr, n, mu, sigma, out, dtype, S(stream), d_consumed, words);
+    return polar_common(0, seed, offset, nullptr, n, mu, sigma, out, dtype, S(stream), d_consumed, words);
 }
 
 int nrng_batched_plan(int method, uint32_t nstreams, const uint64_t *d_n, const uint64_t *d_out_off,
@@ -472,7 +487,7 @@ int nrng_batched_plan(int method, uint32_t nstreams, const uint64_t *d_n, const 
 {
     if (!dtype_ok(dtype))
         return NRNG_EDTYPE;
-    if (method != NRNG_METHOD_B1 && method != NRNG_METHOD_POLAR)
+    if (!method_ok(method))
         return NRNG_EINVAL;
     if (nstreams == 0)
         return NRNG_OK;
@@ -546,7 +561,7 @@ int nrng_batched_exec_part(int part, int method, uint32_t nstreams, const uint64
         return NRNG_EINVAL;
     if (!dtype_ok(dtype))
         return NRNG_EDTYPE;
-    if (method != NRNG_METHOD_B1 && method != NRNG_METHOD_POLAR)
+    if (!method_ok(method))
         return NRNG_EINVAL;
     if (nstreams == 0)
         return NRNG_OK;
@@ -599,10 +614,11 @@ int nrng_batched_exec_part(int part, int method, uint32_t nstreams, const uint64
     a.mus = d_mu;
     a.sigmas = d_sigma;
     a.consumed_arr = d_consumed;
-    const uint32_t gm = persistent_grid(*d, polar_mask_blocks_per_cu(*d, MODE_BATCHED, tu.vi), 0, 0);
+    const int vm = method_vm(method);
+    const uint32_t gm = persistent_grid(*d, polar_mask_blocks_per_cu(*d, MODE_BATCHED, vm, tu.vi), 0, 0);
     const uint32_t gg =
-        persistent_grid(*d, polar_blocks_per_cu(*d, MODE_BATCHED, dtype, tu.vi), tu.grid_per_cu, 0);
-    return hip_status(launch_polar(MODE_BATCHED, dtype, tu.vi, a, gm, gg, s, part));
+        persistent_grid(*d, polar_blocks_per_cu(*d, MODE_BATCHED, vm, dtype, tu.vi), tu.grid_per_cu, 0);
+    return hip_status(launch_polar(MODE_BATCHED, vm, dtype, tu.vi, a, gm, gg, s, part));
 }
 
 int nrng_batched(int method, uint32_t nstreams, const uint64_t *d_seed, const uint64_t *d_offset,
@@ -611,7 +627,7 @@ int nrng_batched(int method, uint32_t nstreams, const uint64_t *d_seed, const ui
 {
     if (!dtype_ok(dtype))
         return NRNG_EDTYPE;
-    if (method != NRNG_METHOD_B1 && method != NRNG_METHOD_POLAR)
+    if (!method_ok(method))
         return NRNG_EINVAL;
     if (nstreams == 0)
         return NRNG_OK;
@@ -777,7 +793,23 @@ int nrng_test_polar_xy(const int32_t *d_xy, uint64_t ncand, double mu, double si
         return NRNG_OK;
     if (!d_xy || !out || !d_mask_words || !d_count)
         return NRNG_EINVAL;
-    return polar_hook(MODE_XY, 0, 0, ncand, d_xy, mu, sigma, out, dtype, d_mask_words, nullptr, d_count,
+    return polar_hook(MODE_XY, 0, 0, 0, ncand, d_xy, mu, sigma, out, dtype, d_mask_words, nullptr, d_count,
+                      S(stream));
+}
+
+int nrng_test_polar2_xy(const int32_t *d_xy, uint64_t ncand, double mu, double sigma, void *out, int dtype,
+                        uint64_t *d_mask_words, uint64_t *d_count, void *stream)
+{
+    if (!dtype_ok(dtype))
+        return NRNG_EDTYPE;
+    int rc = check_mu_sigma(mu, sigma);
+    if (rc)
+        return rc;
+    if (ncand == 0)
+        return NRNG_OK;
+    if (!d_xy || !out || !d_mask_words || !d_count)
+        return NRNG_EINVAL;
+    return polar_hook(MODE_XY, 1, 0, 0, ncand, d_xy, mu, sigma, out, dtype, d_mask_words, nullptr, d_count,
                       S(stream));
 }
 
@@ -788,7 +820,7 @@ int nrng_polar_trace(uint64_t seed, uint64_t offset, uint64_t ncand, uint64_t *d
         return NRNG_OK;
     if (!d_mask_words || !d_word_prefix)
         return NRNG_EINVAL;
-    return polar_hook(MODE_TRACE, seed, offset, ncand, nullptr, 0.0, 1.0, nullptr, NRNG_F32, d_mask_words,
+    return polar_hook(MODE_TRACE, 0, seed, offset, ncand, nullptr, 0.0, 1.0, nullptr, NRNG_F32, d_mask_words,
                       d_word_prefix, nullptr, S(stream));
 }
 

@@ -1,14 +1,15 @@
 // nrng_device.hpp -- device-side building blocks of the normal-deviate
 // kernels for gfx950: the counter-based uniform source, the per-pair
 // transforms of Box-Muller (Algorithm B1) and the Polar method (Algorithm P)
-// [Brent 1993, Section 2], output conversion and store helpers, and the
-// wavefront primitives of the Polar compaction.
+// [Brent 1993, Section 2] and of method P2 (Section 4), output conversion
+// and store helpers, and the wavefront primitives of the Polar compaction.
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 #include "nrng_launch.hpp"
+#include "nrng_p2_poly.hpp"
 
 namespace nrng {
 
@@ -299,6 +300,72 @@ __device__ __forceinline__ void polar_value_f32(int32_t X, int32_t Y, uint64_t S
     const float r = polar_small(S) ? polar_r_small(S, sigma) : polar_r_f32(S, k2);
     zx = __builtin_fmaf(r, (float)X * 0x1p-31f, mu);
     zy = __builtin_fmaf(r, (float)Y * 0x1p-31f, mu);
+}
+
+// ---------------------------------------------------------------------------
+// Method P2 (Section 4).  Same candidates as Algorithm P; step 3 rejects only
+// s >= 1 (S >= 2^62), so S = 0 is kept (its value is (mu, mu)).  The radius
+// factor is sigma sqrt(2) g(s), g(s) = sqrt(-ln(1 - s) / s): for s <= 8/9 a
+// polynomial h(v) in v = (6 s - 4) / (4 - 3 s) (Section 3, rho = 1), for
+// s > 8/9 the logarithm and square root.  Outputs x r sqrt(2) + mu and
+// y r sqrt(2) + mu.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool polar2_accept(uint64_t S) { return S < (1ull << 62); }
+
+// The split s > 8/9, for s = RNE_double(S) 2^-62, as an integer test.
+// 8/9 rounded to double, times 2^62, is an integer multiple of 2^9, and
+// RNE_double(S) is a multiple of 2^9 for S in [2^61, 2^62), so
+// RNE_double(S) <= that value iff S <= it + 256 when the tie at + 256 rounds
+// down (to an even multiple), else iff S <= it + 255.
+constexpr uint64_t kP2TauS = (uint64_t)((8.0 / 9.0) * 0x1p62);
+constexpr uint64_t kP2SplitS = kP2TauS + 256 - ((kP2TauS >> 9) & 1);
+__device__ __forceinline__ bool polar2_big(uint64_t S) { return S > kP2SplitS; }
+
+// FP64 value, in the order of the steps with no fused operations except in
+// the polynomial (Horner's rule with FMA).
+__device__ __forceinline__ void polar2_value_f64(int32_t X, int32_t Y, uint64_t S, double mu, double sigma,
+                                                 double& zx, double& zy)
+{
+    const double s = __dmul_rn((double)S, 0x1p-62);
+    double r;
+    if (s > 8.0 / 9.0) {
+        r = __dmul_rn(sigma, sqrt(__ddiv_rn(-log(__dsub_rn(1.0, s)), s)));
+    } else {
+        const double v = __ddiv_rn(__dsub_rn(__dmul_rn(6.0, s), 4.0), __dsub_rn(4.0, __dmul_rn(3.0, s)));
+        double h = kP2PolyF64[kP2PolyF64Deg];
+#pragma unroll
+        for (int k = kP2PolyF64Deg - 1; k >= 0; --k)
+            h = __builtin_fma(h, v, kP2PolyF64[k]);
+        r = __dmul_rn(sigma, h);
+    }
+    const double rt = __dmul_rn(r, 1.4142135623730951);   // sqrt(2) rounded to double
+    zx = __dadd_rn(__dmul_rn(rt, __dmul_rn((double)X, 0x1p-31)), mu);
+    zy = __dadd_rn(__dmul_rn(rt, __dmul_rn((double)Y, 0x1p-31)), mu);
+}
+
+// FP32 radius factor times 2^-31: sigma sqrt(2) g(s) 2^-31.  ks31 =
+// sigma sqrt(2) 2^-31 and k2 = -2 ln 2 sigma^2.  Both branches are formed
+// and one is selected (in a wave of 64 lanes both are almost always needed).
+//  * s <= 8/9: s from the top word of S (absolute error below 2^-30; h has
+//    no singularity there, so only absolute accuracy matters), v by one
+//    reciprocal, h by Horner's rule with the degree-9 coefficients.
+//  * s > 8/9: 1 - s = (2^62 - S) 2^-62 exactly, rounded once, so
+//    -ln(1 - s) has full relative accuracy, and
+//    g(s) sqrt(2) sigma = sqrt(log2(1 - s) k2 / s).
+__device__ __forceinline__ float polar2_r31_f32(uint64_t S, float ks31, float k2)
+{
+    const float hf = cvt_f32_u32((uint32_t)(S >> 32));     // S 2^-32 = s 2^30
+    const float num = __builtin_fmaf(hf, 6.0f * 0x1p-30f, -4.0f);
+    const float den = __builtin_fmaf(hf, -3.0f * 0x1p-30f, 4.0f);
+    const float v = num * __builtin_amdgcn_rcpf(den);
+    float h = kP2PolyF32[kP2PolyF32Deg];
+#pragma unroll
+    for (int k = kP2PolyF32Deg - 1; k >= 0; --k)
+        h = __builtin_fmaf(h, v, kP2PolyF32[k]);
+    const float tf = u64_to_f32_scaled((1ull << 62) - S, 0x1p-30f, 0x1p-62f);   // 1 - s
+    const float sf = hf * 0x1p-30f;
+    const float rl = __builtin_amdgcn_sqrtf(__builtin_amdgcn_logf(tf) * k2 * __builtin_amdgcn_rcpf(sf));
+    return polar2_big(S) ? rl * 0x1p-31f : h * ks31;
 }
 
 // ---------------------------------------------------------------------------

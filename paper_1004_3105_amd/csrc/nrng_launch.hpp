@@ -93,14 +93,15 @@ int launch_b1_single(int dtype, int vi, const B1Args &a, uint32_t grid, hipStrea
 int launch_b1_words(int dtype, const B1Args &a, uint64_t npairs, hipStream_t s);
 int launch_b1_batched(int dtype, int vi, const B1Args &a, uint32_t grid, hipStream_t s);
 // Polar: the mask, scan and generate kernels, in that order on stream s.
-// grid_mask / grid_gen are the persistent grid sizes of the first and last.
-// part 0 launches all three, 1 the mask and scan kernels, 2 the generate
-// kernel.
-int launch_polar(int mode, int dtype, int vi, const PolarArgs &a, uint32_t grid_mask, uint32_t grid_gen,
+// vm selects the value method: 0 = Algorithm P, 1 = method P2 (no trace
+// mode).  grid_mask / grid_gen are the persistent grid sizes of the first and
+// last.  part 0 launches all three, 1 the mask and scan kernels, 2 the
+// generate kernel.
+int launch_polar(int mode, int vm, int dtype, int vi, const PolarArgs &a, uint32_t grid_mask, uint32_t grid_gen,
                  hipStream_t s, int part = 0);
 int launch_prep(const PrepArgs &a, hipStream_t s);
-int occupancy_polar(int mode, int dtype, int vi, int *blocks_per_cu);        // generate kernel
-int occupancy_polar_mask(int mode, int vi, int *blocks_per_cu);
+int occupancy_polar(int mode, int vm, int dtype, int vi, int *blocks_per_cu);        // generate kernel
+int occupancy_polar_mask(int mode, int vm, int vi, int *blocks_per_cu);
 int occupancy_b1(int batched, int dtype, int vi, int *blocks_per_cu);
 int launch_probe_store(void *out, uint64_t nbytes, uint32_t grid, hipStream_t s);
 int launch_probe_copy(void *dst, const void *src, uint64_t nbytes, uint32_t grid, hipStream_t s);

@@ -20,6 +20,8 @@ long vectors"):
 """
 from __future__ import annotations
 
+import math
+
 import numpy as np
 
 BATCH_SEED = 0xBA7C4
@@ -98,6 +100,38 @@ def polar_edge_xy(seed: int = 13) -> np.ndarray:
     ring = np.clip(ring, -R, R - 1).astype(np.int64)
     uni = g.integers(-R, R, (8192, 2))
     allp = np.concatenate([np.array(pts, dtype=np.int64), small, ring, uni]).astype(np.int64)
+    return allp.astype(np.int32).reshape(-1)
+
+
+def polar2_edge_xy(seed: int = 14) -> np.ndarray:
+    """Explicit int32 candidate pairs for the P2 test hook: the Polar edge
+    points (which include the origin, accepted by P2), the origin repeated
+    inside a word, points whose S = X^2 + Y^2 lies within a few units of
+    the split s = 8/9 on both sides, and random points with s in (8/9, 1)
+    and in [0, 8/9]."""
+    g = rng(seed)
+    R = 1 << 31
+    base = polar_edge_xy(seed).reshape(-1, 2).astype(np.int64)
+    T = (8 * (1 << 62)) // 9
+    pts = [(0, 0)] * 5
+    # integer points whose S lies within 300 of 8/9 * 2^62, on both sides
+    # (found by a search over y; listed so that no search runs here)
+    pts += [(2022265419, 98585171), (1993305295, 354979523), (1979349560, 425971572),
+            (2021405624, 114872817), (1877914036, 756779581), (1985012704, 398749327),
+            (1950686167, 542309818), (1854306938, 812909737), (1880615526, 750041135),
+            (1817986653, 891179550), (2022347770, 96881154), (2016019230, 186930268)]
+    for y in list(range(0, 64)) + [int(v) for v in g.integers(0, 1 << 28, 64)]:
+        x = math.isqrt(T - y * y)
+        for d in (-1, 0, 1, 2):
+            pts.append((x + d, y))
+            pts.append((-(x + d), -y))
+    th = g.uniform(0, 2 * np.pi, 4096)
+    rad = R * np.sqrt(g.uniform(8.0 / 9.0, 1.0, 4096))
+    high = np.stack([np.floor(rad * np.cos(th)), np.floor(rad * np.sin(th))], axis=1)
+    high = np.clip(high, -R, R - 1).astype(np.int64)
+    rad = R * np.sqrt(g.uniform(0.0, 8.0 / 9.0, 4096))
+    low = np.stack([np.floor(rad * np.cos(th)), np.floor(rad * np.sin(th))], axis=1).astype(np.int64)
+    allp = np.concatenate([base, np.array(pts, dtype=np.int64), high, low])
     return allp.astype(np.int32).reshape(-1)
 
 

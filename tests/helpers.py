@@ -76,6 +76,19 @@ def fp64_scaled_tol(z_ref: np.ndarray, mu, sigma) -> np.ndarray:
     return 4.0 * np.spacing(scale)
 
 
+def fp64_p2_tol(z_ref: np.ndarray, mu, sigma) -> np.ndarray:
+    """FP64 bar for method P2: the 4-ulp bar of fp64_scaled_tol plus
+    4e-15 sigma |n|.  The two sides evaluate the same degree-15 polynomial
+    h(v) differently: the oracle sums the Chebyshev series by the three-term
+    recurrence (measured error up to 6.7e-16 against 40-digit evaluation),
+    the kernel uses Horner's rule on the monomial coefficients (2.2e-16);
+    h >= 1, so their relative disagreement stays below about 1e-15, and the
+    extra 4e-15 sigma |n| leaves a factor of four."""
+    z = np.asarray(z_ref, dtype=np.float64)
+    mu = np.asarray(mu, dtype=np.float64)
+    return fp64_scaled_tol(z, mu, sigma) + 4e-15 * np.abs(z - mu)
+
+
 def ulp_of(x: np.ndarray, dtype) -> np.ndarray:
     """Spacing of the target format at |x| (normal and subnormal range)."""
     x = np.abs(np.asarray(x, dtype=np.float64))

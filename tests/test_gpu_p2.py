@@ -1,0 +1,204 @@
+"""GPU parity of method P2 (Section 4 of the paper: the Polar method with
+the radius factor sigma sqrt(2) g(s), g(s) = sqrt(-ln(1 - s)/s), a
+polynomial in v = (6s - 4)/(4 - 3s) for s <= 8/9) against the FP64 oracle,
+through the C ABI.
+
+Bars: accept masks, output indices and consumed counts bit-exact; FP64
+within 4 ulp plus 4e-15 sigma |n| (helpers.fp64_p2_tol: the two sides
+evaluate the degree-15 polynomial by different schemes); FP32 within
+2e-6 max(1, |z|) (widened by |mu| and sigma |n| when mu != 0); BF16/FP16
+within one unit of the format plus the FP32 bar."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import synth
+from gpu_util import NAME, TDT, assert_close, case, dev, host, run, u64
+from helpers import stat_bounds
+from paper_1004_3105_amd import binding as nb
+
+pytestmark = pytest.mark.gpu
+
+FLOAT_DTYPES = [nb.NRNG_F64, nb.NRNG_F32, nb.NRNG_BF16, nb.NRNG_F16]
+
+
+def test_p2_f64_stream():
+    n = (1 << 22) + 1
+    ref, used = O.polar2(7, 0, n)
+    zt, cons = run("polar2", 7, 0, n, nb.NRNG_F64, with_consumed=True)
+    assert cons == used
+    assert_close(host(zt), ref, nb.NRNG_F64, what="p2 f64", p2=True)
+
+
+@pytest.mark.parametrize("seed,offset,mu,sigma", [(7, 0, 0.0, 1.0), (0xC0FFEE, 999, -4.0, 3.0)])
+def test_p2_f32_stream(seed, offset, mu, sigma):
+    n = (1 << 24) + 1
+    ref, used = O.polar2(seed, offset, n, mu, sigma)
+    zt, cons = run("polar2", seed, offset, n, nb.NRNG_F32, mu, sigma, with_consumed=True)
+    assert cons == used
+    assert_close(host(zt), ref, nb.NRNG_F32, mu, sigma, what="p2 f32")
+
+
+@pytest.mark.parametrize("dtype", [nb.NRNG_BF16, nb.NRNG_F16])
+def test_p2_half_stream(dtype):
+    n = (1 << 18) + 1
+    ref, used = O.polar2(17, 4, n, -1.0, 0.75)
+    zt, cons = run("polar2", 17, 4, n, dtype, -1.0, 0.75, with_consumed=True)
+    assert cons == used
+    assert_close(host(zt), ref, dtype, -1.0, 0.75, what="p2 half")
+    z32 = run("polar2", 17, 4, n, nb.NRNG_F32, -1.0, 0.75)
+    assert torch.equal(zt, z32.to(TDT[dtype]))
+
+
+@pytest.mark.parametrize("dtype", FLOAT_DTYPES)
+def test_p2_xy_edge_cases(dtype):
+    """The origin (accepted by P2), the circle S = 2^62, points within a few
+    hundred units of S = 8/9 2^62 on both sides of the split, tiny s, and
+    random points on each side of the split."""
+    xy = synth.polar2_edge_xy()
+    ncand = xy.size // 2
+    ref, masks, a = O.polar2_xy(xy)
+    d = dev()
+    xt = torch.from_numpy(xy).to(d)
+    out = torch.empty(2 * ncand, dtype=TDT[dtype], device=d)
+    gm = torch.zeros((ncand + 63) // 64, dtype=torch.int64, device=d)
+    cnt = torch.zeros(1, dtype=torch.int64, device=d)
+    case("p2 xy", NAME[dtype], ncand)
+    nb.nrng_test_polar2_xy(xt, ncand, 0.0, 1.0, out, dtype, gm, cnt)
+    torch.cuda.synchronize()
+    assert np.array_equal(u64(gm), masks)
+    assert int(cnt.item()) == a
+    assert_close(host(out[:2 * a]), ref, dtype, what="p2 xy", p2=True)
+
+
+def test_p2_hand_values_through_gpu():
+    """The closed-form rows of the oracle's P2 fixture, computed by the FP64
+    kernel: the same budgets as the oracle's pin (abs:3e-11 for s <= 8/9,
+    4 ulp for s > 8/9)."""
+    from helpers import closed_form, golden_rows, ulp_dist64
+    rows = golden_rows("polar2_hand_values.txt")
+    xy = np.array([[int(r[0]), int(r[1])] for r in rows], dtype=np.int64).astype(np.int32).reshape(-1)
+    d = dev()
+    n = len(rows)
+    out = torch.empty(2 * n, dtype=torch.float64, device=d)
+    gm = torch.zeros((n + 63) // 64, dtype=torch.int64, device=d)
+    cnt = torch.zeros(1, dtype=torch.int64, device=d)
+    case("p2 hand values", n)
+    nb.nrng_test_polar2_xy(torch.from_numpy(xy).to(d), n, 0.0, 1.0, out, nb.NRNG_F64, gm, cnt)
+    torch.cuda.synchronize()
+    acc = [int(r[2]) for r in rows]
+    assert int(cnt.item()) == sum(acc)
+    vals = host(out[:2 * sum(acc)]).reshape(-1, 2)
+    k = 0
+    for r in rows:
+        if r[2] == "0":
+            continue
+        kind, amt = r[5].split(":")
+        for c in range(2):
+            want, got = closed_form(r[3 + c]), vals[k, c]
+            if kind == "abs" or want == 0.0:
+                assert abs(got - want) <= float(amt), (r, c, got, want)
+            else:
+                assert ulp_dist64([got], [want])[0] <= int(amt), (r, c, got, want)
+        k += 1
+
+
+def test_p2_offsets_alignment_small_n():
+    d = dev()
+    for dtype in FLOAT_DTYPES:
+        full, used = run("polar2", 9, 50, 5001, dtype, with_consumed=True)
+        head, u1 = run("polar2", 9, 50, 1000, dtype, with_consumed=True)
+        tail, u2 = run("polar2", 9, 50 + u1, 4001, dtype, with_consumed=True)
+        assert torch.equal(torch.cat([head, tail]), full) and u1 + u2 == used
+        buf = torch.zeros(5001 + 3, dtype=TDT[dtype], device=d)
+        for sh in (1, 2, 3):
+            o = buf[sh:sh + 5001]
+            run("polar2", 9, 50, 5001, dtype, out=o)
+            assert torch.equal(o, full)
+        for n in (1, 2, 3, 7):
+            z, c = run("polar2", 9, 50, n, dtype, with_consumed=True)
+            assert c == O.polar2(9, 50, n)[1]
+            assert torch.equal(z, full[:n])
+    z = run("polar2", 9, 0, 999, nb.NRNG_F32, -2.0, 0.0)
+    assert torch.all(z == -2.0)
+
+
+def test_p2_same_candidates_as_polar():
+    """P2 and Algorithm P consume the same candidates (no (0, 0) occurs in
+    this stream), so their consumed counts agree; the values differ."""
+    zp, cp = run("polar", 31, 0, 1 << 20, nb.NRNG_F32, with_consumed=True)
+    z2, c2 = run("polar2", 31, 0, 1 << 20, nb.NRNG_F32, with_consumed=True)
+    assert cp == c2
+    assert not torch.equal(zp, z2)
+    assert torch.equal(torch.sign(zp), torch.sign(z2))
+
+
+def test_p2_batched_matches_oracle():
+    d = dev()
+    cfg = synth.batched_streams(96, n_lo=1.0, n_hi=2e4)
+    ns, total = 96, cfg["total"]
+    D = {k: torch.from_numpy(cfg[k].view(np.int64) if cfg[k].dtype == np.uint64 else cfg[k]).to(d)
+         for k in ("seed", "offset", "n", "mu", "sigma")}
+    for dtype in (nb.NRNG_F64, nb.NRNG_F32):
+        out = torch.empty(total, dtype=TDT[dtype], device=d)
+        cons = torch.zeros(ns, dtype=torch.int64, device=d)
+        case("p2 batched", NAME[dtype], ns, total)
+        nb.nrng_batched(nb.NRNG_METHOD_P2, ns, D["seed"], D["offset"], D["n"], None, D["mu"], D["sigma"], out,
+                        total, dtype, None, cons)
+        torch.cuda.synchronize()
+        c = u64(cons)
+        z = host(out)
+        for j in range(ns):
+            n, o0 = int(cfg["n"][j]), int(cfg["out_off"][j])
+            mu, sg = float(cfg["mu"][j]), float(cfg["sigma"][j])
+            ref, used = O.polar2(int(cfg["seed"][j]), int(cfg["offset"][j]), n, mu, sg)
+            assert int(c[j]) == used, j
+            assert_close(z[o0:o0 + n], ref, dtype, mu, sg, what="p2 batched stream %d" % j, p2=True)
+
+
+def test_p2_results_do_not_depend_on_launch_variant():
+    for dtype in (nb.NRNG_F64, nb.NRNG_F32):
+        saved = nb.nrng_tune_get(nb.KERNEL_POLAR, dtype)
+        outs = []
+        try:
+            for wg, un in nb.nrng_tune_variants(nb.KERNEL_POLAR):
+                for gpc in (0, 1):
+                    nb.nrng_tune_set(nb.KERNEL_POLAR, dtype, wg, un, gpc)
+                    outs.append(run("polar2", 21, 8, 300007, dtype, with_consumed=True))
+        finally:
+            nb.nrng_tune_set(nb.KERNEL_POLAR, dtype, *saved)
+        assert len({c for _, c in outs}) == 1
+        for o, _ in outs[1:]:
+            assert torch.equal(o, outs[0][0])
+
+
+def test_p2_gpu_output_distribution():
+    from scipy import stats
+    n = 1 << 22
+    z = host(run("polar2", 12345, 0, n, nb.NRNG_F32))
+    bd = stat_bounds(n)
+    assert abs(z.mean()) < bd["mean"]
+    assert abs(z.var() - 1) < bd["var"]
+    assert abs(stats.skew(z)) < bd["skew"]
+    assert abs(stats.kurtosis(z, fisher=False) - 3) < bd["kurt"]
+    assert stats.kstest(z, "norm").statistic < bd["ks"]
+    # (zx^2 + zy^2) / 2 = -ln(1 - s) is exponential(1)
+    e = 0.5 * (z[0::2] ** 2 + z[1::2] ** 2)
+    assert stats.kstest(e, "expon").statistic < 1.95 / np.sqrt(e.size)
+
+
+def test_p2_error_report(capsys):
+    """Largest error against the oracle per dtype on the first 2^22 normals of
+    the seed-7 stream (printed; asserted within the bars)."""
+    n = 1 << 22
+    ref, _ = O.polar2(7, 0, n)
+    rows = []
+    for dtype in FLOAT_DTYPES:
+        z = host(run("polar2", 7, 0, n, dtype))
+        frac = assert_close(z, ref, dtype, what="p2 %s" % NAME[dtype], p2=True)
+        rel = float(np.max(np.abs(z - ref) / np.maximum(1.0, np.abs(ref))))
+        rows.append("p2 %-4s max|dz|/max(1,|z|) %.3e  %s" % (
+            NAME[dtype], rel, ("max ulp %d" % frac) if dtype == nb.NRNG_F64 else ("max err/bar %.3f" % frac)))
+    with capsys.disabled():
+        print("\n[P2 error report, n = 2^22]\n" + "\n".join(rows), flush=True)
