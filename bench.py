@@ -12,8 +12,9 @@ with every input resident in GPU memory before timing starts.
 Alongside, outside the timed region: the measured store-only and hash-only
 ceilings, the single-stream fills of 2^30 normals (FP32, BF16, FP16 and the
 plain FP64 kernels, the comparison point of the FP32 batched figure), the
-graph-replayed repeated fill (64 x 2^28 Polar normals), and the CPU oracle
-timed on the host cores.
+graph-replayed repeated fill (64 x 2^28 Polar normals), method P2 (Section
+4) on the same batched workload, and the CPU oracle timed on the host
+cores.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extras]
                        [--no-cpu] [--only b1|polar]
@@ -50,11 +51,21 @@ VALU_PEAK_TOPS = 39.32
 #   b1_batched:     per pair: hash of u 18 + hash of v (top word) 17 +
 #                   ln(1 - u) with the exact complement 21 + angle reduction,
 #                   conversion, sin, cos 9 + 2 FMAs
-ALU_OPS = {"polar_count": 38, "polar_generate": 63, "b1_batched": 67}
-ALU_UNIT = {"polar_count": "candidate", "polar_generate": "output pair", "b1_batched": "output pair"}
+#   p2_count:       per candidate: as polar_count with the one-sided test
+#                   S < 2^62 (1)
+#   p2_generate:    per pair: 2 hashes 34 + S 2 + s from the top word 1 +
+#                   v = (6s - 4)/(4 - 3s) 4 + degree-9 Horner 9 + split test
+#                   and select 2 + the library branch for s > 8/9 (10
+#                   operations, taken by 1/9 of the pairs) 1 + scaling 1 +
+#                   2 conversions and 2 FMAs 4
+ALU_OPS = {"polar_count": 38, "polar_generate": 63, "b1_batched": 67, "p2_count": 37, "p2_generate": 58}
+ALU_UNIT = {"polar_count": "candidate", "polar_generate": "output pair", "b1_batched": "output pair",
+            "p2_count": "candidate", "p2_generate": "output pair"}
 KERNEL_NAMES = {"polar_count": "polar_mask_kernel<MODE_BATCHED> + polar_scan_kernel",
                 "polar_generate": "polar_gen_kernel<float, MODE_BATCHED>",
-                "b1_batched": "b1_batched_kernel<float>"}
+                "b1_batched": "b1_batched_kernel<float>",
+                "p2_count": "polar_mask_kernel<MODE_BATCHED, VM_P2> + polar_scan_kernel",
+                "p2_generate": "polar_gen_kernel<float, MODE_BATCHED, VM_P2>"}
 PROFILES = os.path.join(ROOT, "profiles")
 
 
@@ -103,8 +114,9 @@ def main() -> int:
     ap.add_argument("--nstreams", type=int, default=4096)
     ap.add_argument("--no-extras", action="store_true", help="skip the side measurements")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--only", choices=["b1", "polar"], default=None,
-                    help="time one method only (for profiling runs)")
+    ap.add_argument("--only", choices=["b1", "polar", "p2"], default=None,
+                    help="time one method only (for profiling runs; p2 = method P2 of Section 4, which is "
+                         "otherwise measured among the extras)")
     ap.add_argument("--calibrate", action="store_true",
                     help="also run a 1 GiB copy and a 1 GiB store probe once (known traffic, for scaling "
                          "hardware byte counters in profiling runs)")
@@ -142,7 +154,9 @@ def main() -> int:
         "sigma": torch.from_numpy(cfg["sigma"]).to(dev),
     }
     methods = [("b1", nb.NRNG_METHOD_B1), ("polar", nb.NRNG_METHOD_POLAR)]
-    if args.only:
+    if args.only == "p2":
+        methods = [("p2", nb.NRNG_METHOD_P2)]
+    elif args.only:
         methods = [m for m in methods if m[0] == args.only]
     outs = {name: torch.empty(total, dtype=torch.float32, device=dev) for name, _ in methods}
     cons = {name: torch.zeros(ns, dtype=torch.int64, device=dev) for name, _ in methods}
@@ -191,13 +205,13 @@ def main() -> int:
         per_kernel[name] = {"plan_ms": round(plan_ms, 5), "exec_ms": round(exec_ms, 5),
                             "normals_per_s": total / (exec_ms * 1e-3), "write_GBps": round(gbs, 1),
                             "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)}
-        if name == "polar":
+        if name in ("polar", "p2"):
             cand = int(u64sum(cons[name])) // 2       # candidates the method evaluates
             per_kernel[name]["count_ms"] = round(count_ms, 5)
             per_kernel[name]["generate_ms"] = round(gen_ms, 5)
             per_kernel[name]["candidates"] = cand
-            units = {"polar_count": (count_ms, ALU_OPS["polar_count"] * cand),
-                     "polar_generate": (gen_ms, ALU_OPS["polar_generate"] * pairs)}
+            units = {name + "_count": (count_ms, ALU_OPS[name + "_count"] * cand),
+                     name + "_generate": (gen_ms, ALU_OPS[name + "_generate"] * pairs)}
         else:
             units = {"b1_batched": (gen_ms, ALU_OPS["b1_batched"] * pairs)}
         for k, (ms, ops) in units.items():
@@ -249,10 +263,58 @@ def main() -> int:
         del src, dst
     if not args.no_extras:
         result["extras"] = extras(nb, torch, dev, stream, per_kernel, value)
+        if args.only != "p2":
+            result["extras"]["p2_batched"] = p2_batched(nb, torch, stream, D, cfg, ns, total, pairs, args.steps,
+                                                        per_kernel)
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(cfg, [m for m, _ in methods])
     print(json.dumps(result), flush=True)
     return 0
+
+
+def p2_batched(nb, torch, stream, D, cfg, ns, total, pairs, steps, per_kernel):
+    """Method P2 (Section 4) on the same batched workload, timed like the
+    step's Polar leg: plan, then the mask + scan kernels and the generate
+    kernel between events."""
+    out = torch.empty(total, dtype=torch.float32, device=D["n"].device)
+    cons = torch.zeros(ns, dtype=torch.int64, device=D["n"].device)
+    m = nb.NRNG_METHOD_P2
+
+    def once(ev=None):
+        if ev is not None:
+            ev[0].record(stream)
+        nb.nrng_batched_plan(m, ns, D["n"], None, total, nb.NRNG_F32, stream, cons)
+        for part in (1, 2):
+            if ev is not None:
+                ev[part].record(stream)
+            nb.nrng_batched_exec_part(part, m, ns, D["seed"], D["offset"], D["n"], None, D["mu"], D["sigma"], out,
+                                      nb.NRNG_F32, stream, cons)
+        if ev is not None:
+            ev[3].record(stream)
+
+    for _ in range(3):
+        once()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+    for s in range(steps):
+        once(evs[s])
+    torch.cuda.synchronize()
+
+    def avg(a, b):
+        return sum(evs[s][a].elapsed_time(evs[s][b]) for s in range(steps)) / steps
+
+    plan_ms, count_ms, gen_ms = avg(0, 1), avg(1, 2), avg(2, 3)
+    exec_ms = count_ms + gen_ms
+    cand = int(u64sum(cons)) // 2
+    r = {"plan_ms": round(plan_ms, 5), "count_ms": round(count_ms, 5), "generate_ms": round(gen_ms, 5),
+         "exec_ms": round(exec_ms, 5), "normals_per_s": total / (exec_ms * 1e-3),
+         "write_GBps": round(4.0 * total / (exec_ms * 1e-3) / 1e9, 1), "candidates": cand, "alu": {}}
+    for k, (ms, ops) in {"p2_count": (count_ms, ALU_OPS["p2_count"] * cand),
+                         "p2_generate": (gen_ms, ALU_OPS["p2_generate"] * pairs)}.items():
+        r["alu"][k] = {"ms": round(ms, 5), "Tops_per_s": round(ops / (ms * 1e-3) / 1e12, 2),
+                       "frac_valu_peak": round(ops / (ms * 1e-3) / 1e12 / VALU_PEAK_TOPS, 4)}
+    if "polar" in per_kernel:
+        r["exec_vs_polar"] = round(per_kernel["polar"]["exec_ms"] / exec_ms, 4)
+    return r
 
 
 def extras(nb, torch, dev, stream, per_kernel, batched_value):
@@ -297,6 +359,8 @@ def extras(nb, torch, dev, stream, per_kernel, batched_value):
         ms = timed(lambda: nb.nrng_polar(7, 0, n, 0.0, 1.0, out, dt, stream, None), 5)
         r["polar_normals_per_s"] = n / (ms * 1e-3)
         r["polar_write_GBps"] = round(n * nbytes_el / (ms * 1e-3) / 1e9, 1)
+        ms = timed(lambda: nb.nrng_polar2(7, 0, n, 0.0, 1.0, out, dt, stream, None), 5)
+        r["p2_normals_per_s"] = n / (ms * 1e-3)
         single[name] = r
         del out
         torch.cuda.empty_cache()
@@ -349,7 +413,7 @@ def cpu_baseline(cfg, methods):
 
     def work(mj):
         m, j = mj
-        fn = O.b1 if m == "b1" else O.polar
+        fn = {"b1": O.b1, "polar": O.polar, "p2": O.polar2}[m]
         fn(int(cfg["seed"][j]), int(cfg["offset"][j]), int(cfg["n"][j]), float(cfg["mu"][j]), float(cfg["sigma"][j]))
         return int(cfg["n"][j])
 
