@@ -302,6 +302,17 @@ __device__ __forceinline__ void polar_value_f32(int32_t X, int32_t Y, uint64_t S
     zy = __builtin_fmaf(r, (float)Y * 0x1p-31f, mu);
 }
 
+// a in the lanes whose bit of m is clear, b in the others.  Written as the
+// instruction because the compiler otherwise turns a select between two
+// costly values into a branch around each, which serialises the pairs a lane
+// computes (in a wave of 64 lanes both sides are almost always needed).
+__device__ __forceinline__ float select_lanes(uint64_t m, float a, float b)
+{
+    float r;
+    asm("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(m));
+    return r;
+}
+
 // ---------------------------------------------------------------------------
 // Method P2 (Section 4).  Same candidates as Algorithm P; step 3 rejects only
 // s >= 1 (S >= 2^62), so S = 0 is kept (its value is (mu, mu)).  The radius
@@ -345,7 +356,7 @@ __device__ __forceinline__ void polar2_value_f64(int32_t X, int32_t Y, uint64_t 
 
 // FP32 radius factor times 2^-31: sigma sqrt(2) g(s) 2^-31.  ks31 =
 // sigma sqrt(2) 2^-31 and k2 = -2 ln 2 sigma^2.  Both branches are formed
-// and one is selected (in a wave of 64 lanes both are almost always needed).
+// in every lane and one is selected.
 //  * s <= 8/9: s from the top word of S (absolute error below 2^-30; h has
 //    no singularity there, so only absolute accuracy matters), v by one
 //    reciprocal, h by Horner's rule with the degree-9 coefficients.
@@ -365,7 +376,7 @@ __device__ __forceinline__ float polar2_r31_f32(uint64_t S, float ks31, float k2
     const float tf = u64_to_f32_scaled((1ull << 62) - S, 0x1p-30f, 0x1p-62f);   // 1 - s
     const float sf = hf * 0x1p-30f;
     const float rl = __builtin_amdgcn_sqrtf(__builtin_amdgcn_logf(tf) * k2 * __builtin_amdgcn_rcpf(sf));
-    return polar2_big(S) ? rl * 0x1p-31f : h * ks31;
+    return select_lanes(__ballot(polar2_big(S)), h * ks31, rl * 0x1p-31f);
 }
 
 // ---------------------------------------------------------------------------
@@ -404,6 +415,36 @@ __device__ __forceinline__ uint64_t uniform_u64(uint64_t v)
     uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
     uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
     return ((uint64_t)hi << 32) | lo;
+}
+
+// Cross-lane moves by DPP over the whole wave64 (GFX9 wave shift / rotate).
+// wave_shr1_keep: lane l > 0 receives src of lane l - 1, lane 0 keeps old.
+// wave_ror1: lane l receives src of lane (l - 1) mod 64 (lane 0 gets lane 63).
+__device__ __forceinline__ uint32_t dpp_shr1_keep_u32(uint32_t old, uint32_t src)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)src, 0x138, 0xF, 0xF, false);
+}
+__device__ __forceinline__ uint32_t dpp_ror1_u32(uint32_t src)
+{
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)src, 0x13C, 0xF, 0xF, false);   // no lane lacks a source
+}
+__device__ __forceinline__ float wave_shr1_keep(float old, float src)
+{
+    return __uint_as_float(dpp_shr1_keep_u32(__float_as_uint(old), __float_as_uint(src)));
+}
+__device__ __forceinline__ float wave_ror1(float src) { return __uint_as_float(dpp_ror1_u32(__float_as_uint(src))); }
+__device__ __forceinline__ double wave_shr1_keep(double old, double src)
+{
+    const uint64_t o = __builtin_bit_cast(uint64_t, old), v = __builtin_bit_cast(uint64_t, src);
+    const uint64_t r = (uint64_t)dpp_shr1_keep_u32((uint32_t)o, (uint32_t)v) |
+                       ((uint64_t)dpp_shr1_keep_u32((uint32_t)(o >> 32), (uint32_t)(v >> 32)) << 32);
+    return __builtin_bit_cast(double, r);
+}
+__device__ __forceinline__ double wave_ror1(double src)
+{
+    const uint64_t v = __builtin_bit_cast(uint64_t, src);
+    const uint64_t r = (uint64_t)dpp_ror1_u32((uint32_t)v) | ((uint64_t)dpp_ror1_u32((uint32_t)(v >> 32)) << 32);
+    return __builtin_bit_cast(double, r);
 }
 
 // Orders one wave's LDS accesses before and after this point for all of its
