@@ -24,6 +24,7 @@ struct DevState {
     uint64_t *masks = nullptr;
     uint64_t word_cap = 0;
     uint32_t *ipfx = nullptr;
+    uint32_t *tile_stream = nullptr;
     uint64_t tile_cap = 0;
     uint32_t *csum = nullptr;
     uint64_t *cpfx = nullptr;
@@ -120,15 +121,18 @@ int ensure_polar_ws(DevState &d, uint64_t tiles, uint64_t words, hipStream_t s)
         return NRNG_EHIP;
     hipFree(d.masks);
     hipFree(d.ipfx);
+    hipFree(d.tile_stream);
     hipFree(d.csum);
     hipFree(d.cpfx);
     d.masks = nullptr;
     d.ipfx = nullptr;
+    d.tile_stream = nullptr;
     d.csum = nullptr;
     d.cpfx = nullptr;
     d.tile_cap = d.word_cap = 0;
     if (hipMalloc(&d.masks, wcap * sizeof(uint64_t)) != hipSuccess ||
         hipMalloc(&d.ipfx, tcap * sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc(&d.tile_stream, tcap * sizeof(uint32_t)) != hipSuccess ||
         hipMalloc(&d.csum, chunks * sizeof(uint32_t)) != hipSuccess ||
         hipMalloc(&d.cpfx, (chunks + 1) * sizeof(uint64_t)) != hipSuccess)
         return NRNG_ENOMEM;
@@ -251,6 +255,7 @@ PolarArgs polar_args(DevState &d)
     std::memset(&a, 0, sizeof(a));
     a.masks = d.masks;
     a.ipfx = d.ipfx;
+    a.tile_stream = d.tile_stream;
     a.csum = d.csum;
     a.cpfx = d.cpfx;
     a.misc = d.misc;

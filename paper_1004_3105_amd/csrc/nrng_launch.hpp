@@ -46,6 +46,7 @@ struct PolarArgs {
     // workspace
     uint64_t *masks;         // accept-mask words, tile t's words at [t U, t U + U)
     uint32_t *ipfx;          // per tile: accepted pairs before it within its chunk
+    uint32_t *tile_stream;   // batched, per tile: its stream (written by the mask kernel)
     uint32_t *csum;          // per chunk: accepted pairs in it
     uint64_t *cpfx;          // per chunk: accepted pairs before it (all streams together)
     uint64_t *misc;          // [0]: the single-stream offset read from *cursor by the scan kernel
