@@ -4,8 +4,8 @@ This package wraps ``nrng_oracle.c`` -- a plain single-threaded C99
 implementation, in IEEE double precision without fused multiply-add, of
 Box-Muller Algorithm B1 and the Polar method (Algorithm P) from Section 2 of
 Brent's "Fast Normal Random Number Generators for Vector Processors" (1993),
-and method P2 of its Section 4, fed by a counter-based SplitMix64 uniform
-stream.
+method B3 of its Section 3 and method P2 of its Section 4, fed by a
+counter-based SplitMix64 uniform stream.
 
 Only the test suite, the smoke check and the CPU-baseline leg of the
 benchmark may import it.  The product library (``paper_1004_3105_amd``)
@@ -77,6 +77,9 @@ def lib():
                 "orc_polar2": (u64, [u64, u64, u64, f64, f64, vp]),
                 "orc_polar2_count": (u64, [u64, u64, u64]),
                 "orc_polar2_window": (u64, [u64, u64, u64, u64, f64, f64, vp]),
+                "orc_b3_u": (None, [vp, vp, vp, u64, f64, f64, vp]),
+                "orc_b3_words": (None, [vp, u64, f64, f64, vp]),
+                "orc_b3": (u64, [u64, u64, u64, f64, f64, vp]),
                 "orc_moments": (None, [vp, u64, vp]),
                 "orc_normal_cdf": (f64, [f64]),
                 "orc_ks": (f64, [vp, u64, ctypes.c_int, f64, f64]),
@@ -309,6 +312,32 @@ def polar2_window(seed: int, offset: int, j0: int, ncand: int, mu: float = 0.0, 
     out = np.empty(max(2 * ncand, 1), dtype=np.float64)
     a = int(lib().orc_polar2_window(seed & M64, offset & M64, j0, ncand, mu, sigma, _p(out)))
     return out[:2 * a]
+
+
+# ---------------------------------------------------------------- B3
+def b3(seed: int, offset: int, n: int, mu: float = 0.0, sigma: float = 1.0):
+    """n normals by method B3; returns (values, uniforms consumed)."""
+    out = np.empty(max(n, 1), dtype=np.float64)
+    used = lib().orc_b3(seed & M64, offset & M64, n, mu, sigma, _p(out))
+    return out[:n], int(used)
+
+
+def b3_u(u1, u2, u3, mu: float = 0.0, sigma: float = 1.0) -> np.ndarray:
+    u1 = np.ascontiguousarray(u1, dtype=np.float64)
+    u2 = np.ascontiguousarray(u2, dtype=np.float64)
+    u3 = np.ascontiguousarray(u3, dtype=np.float64)
+    assert u1.shape == u2.shape == u3.shape
+    out = np.empty(2 * u1.size, dtype=np.float64)
+    lib().orc_b3_u(_p(u1), _p(u2), _p(u3), u1.size, mu, sigma, _p(out))
+    return out
+
+
+def b3_words(words, mu: float = 0.0, sigma: float = 1.0) -> np.ndarray:
+    w = np.ascontiguousarray(words, dtype=np.uint64)
+    assert w.size % 3 == 0
+    out = np.empty(2 * (w.size // 3), dtype=np.float64)
+    lib().orc_b3_words(_p(w), w.size // 3, mu, sigma, _p(out))
+    return out
 
 
 # ---------------------------------------------------------------- statistics

@@ -1,8 +1,8 @@
 /*
  * nrng_oracle.c -- plain, slow, single-threaded FP64 reference for the
  * normal-deviate path: Box-Muller Algorithm B1 and the Polar method,
- * Algorithm P (Section 2), and method P2 (Section 4, the Polar method with
- * the radius factor of method B3, Section 3) of Brent, "Fast Normal Random
+ * Algorithm P (Section 2), method B3 (Section 3) and method P2 (Section 4,
+ * the Polar method with the radius factor of method B3) of Brent, "Fast Normal Random
  * Number Generators for Vector Processors", 1993.
  *
  * TEST INFRASTRUCTURE ONLY.  Nothing in the product library may include,
@@ -16,7 +16,7 @@
  * multiply-add, so every line below is one IEEE-754 double operation).
  *
  * Pins (see the tests): the SplitMix64 check sequence, closed-form B1,
- * Polar and P2 values for chosen inputs, the paper's error bound of the P2
+ * Polar, P2 and B3 values for chosen inputs, the paper's error bound of the P2
  * polynomial against the closed form, brute-force lattice counts of the Polar
  * acceptance predicate on small grids, the pi/4 acceptance rate, the
  * uniformity of the accepted s, sample moments and a Kolmogorov-Smirnov
@@ -451,6 +451,80 @@ uint64_t orc_polar2_window(uint64_t seed, uint64_t offset, uint64_t j0, uint64_t
         }
     }
     return a;
+}
+
+/* ------------------------------------------------------------------------
+ * Method B3, Section 3.  Box-Muller with f(u) = sqrt(-ln(1 - u)) evaluated
+ * as sqrt(u) g(u) through the same polynomial h(v) as P2, and the square
+ * root avoided by drawing two uniforms: m = max(u1, u2) and u = m^2, which
+ * is again uniform on [0, 1) with sqrt(u) = m.  Per pair:
+ *   1. u1, u2, u3 uniform;  2. m = max(u1, u2), u = m^2;
+ *   3. u > 8/9: r = sigma sqrt(-ln(1 - u)) (library), else
+ *      v = (6u - 4)/(4 - 3u) and r = sigma m h(v);
+ *   4. s = sin(2 pi u3 - pi), c = cos(2 pi u3 - pi);
+ *   5. return mu + c r sqrt(2), then mu + s r sqrt(2).
+ * Pair k takes the three consecutive uniforms 3k, 3k + 1, 3k + 2 of the
+ * stream, so a stream of n values consumes 3 ceil(n/2) uniforms.
+ * --------------------------------------------------------------------- */
+static void b3_pair(const double *c, double u1, double u2, double u3, double mu, double sigma, double *x,
+                    double *y)
+{
+    double m = u1 > u2 ? u1 : u2;
+    double u = m * m;
+    double r;
+    if (u > 8.0 / 9.0) {
+        r = sigma * sqrt(-log(1.0 - u));
+    } else {
+        double v = (6.0 * u - 4.0) / (4.0 - 3.0 * u);
+        r = sigma * m * cheb_sum(c, P2_DEGREE, v);
+    }
+    double t = (2.0 * M_PI) * u3 - M_PI;
+    double rt = r * M_SQRT2;
+    *x = cos(t) * rt + mu;
+    *y = sin(t) * rt + mu;
+}
+
+/* B3 from explicit uniforms: pair p uses (u1[p], u2[p], u3[p]). */
+void orc_b3_u(const double *u1, const double *u2, const double *u3, uint64_t npairs, double mu, double sigma,
+              double *out)
+{
+    double c[P2_DEGREE + 1];
+    orc_p2_cheb(P2_DEGREE, c);
+    for (uint64_t p = 0; p < npairs; ++p)
+        b3_pair(c, u1[p], u2[p], u3[p], mu, sigma, &out[2 * p], &out[2 * p + 1]);
+}
+
+/* B3 from explicit 64-bit hash words, three per pair: u_i = (w >> 11) 2^-53. */
+void orc_b3_words(const uint64_t *w, uint64_t npairs, double mu, double sigma, double *out)
+{
+    double c[P2_DEGREE + 1];
+    orc_p2_cheb(P2_DEGREE, c);
+    for (uint64_t p = 0; p < npairs; ++p) {
+        double u1 = (double)(w[3 * p] >> 11) * 0x1p-53;
+        double u2 = (double)(w[3 * p + 1] >> 11) * 0x1p-53;
+        double u3 = (double)(w[3 * p + 2] >> 11) * 0x1p-53;
+        b3_pair(c, u1, u2, u3, mu, sigma, &out[2 * p], &out[2 * p + 1]);
+    }
+}
+
+/* B3 over the counter stream: n values; returns the uniforms consumed,
+ * 3 ceil(n/2). */
+uint64_t orc_b3(uint64_t seed, uint64_t offset, uint64_t n, double mu, double sigma, double *out)
+{
+    double c[P2_DEGREE + 1];
+    orc_p2_cheb(P2_DEGREE, c);
+    uint64_t npairs = (n + 1) / 2;
+    for (uint64_t k = 0; k < npairs; ++k) {
+        double u1 = orc_uniform(seed, offset + 3 * k);
+        double u2 = orc_uniform(seed, offset + 3 * k + 1);
+        double u3 = orc_uniform(seed, offset + 3 * k + 2);
+        double x, y;
+        b3_pair(c, u1, u2, u3, mu, sigma, &x, &y);
+        out[2 * k] = x;
+        if (2 * k + 1 < n)
+            out[2 * k + 1] = y;
+    }
+    return 3 * npairs;
 }
 
 /* ------------------------------------------------------------------------

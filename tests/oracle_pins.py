@@ -24,7 +24,11 @@ What pins what:
     computed here from the closed form, closed-form values on both sides of
     the split at s = 8/9, the lattice count with the origin accepted, the
     identity z_P2 = z_P sqrt(ln(1 - s)/ln(s)) pair by pair against the Polar
-    stream, and -ln(1 - s) = (zx^2 + zy^2)/2 being exponential(1).
+    stream, and -ln(1 - s) = (zx^2 + zy^2)/2 being exponential(1);
+  * method B3 (Section 3): closed-form values (max rather than min, the
+    order cos then sin, the shift by -pi, both sides of 8/9), the whole
+    stream pair by pair against sqrt(-2 log1p(-m^2)) (cos t, sin t)
+    computed here, 3 uniforms per pair, and the distribution.
 """
 from __future__ import annotations
 
@@ -381,6 +385,68 @@ def check_polar2_distribution(n: int = 1 << 20):
     assert stats.kstest(e, "expon").statistic < 1.95 / math.sqrt(e.size)
 
 
+# ------------------------------------------------------------------ B3
+def check_b3_hand():
+    rows = golden_rows("b3_hand_values.txt")
+    u1 = np.array([closed_form(r[0]) for r in rows])
+    u2 = np.array([closed_form(r[1]) for r in rows])
+    u3 = np.array([closed_form(r[2]) for r in rows])
+    out = O.b3_u(u1, u2, u3).reshape(-1, 2)
+    for k, r in enumerate(rows):
+        kind, amt = r[5].split(":")
+        for c in range(2):
+            want, got = closed_form(r[3 + c]), out[k, c]
+            if kind == "abs" or want == 0.0:
+                assert abs(got - want) <= max(float(amt), 1e-15), (r, c, got, want)
+            else:
+                assert ulp_dist64([got], [want])[0] <= int(amt), (r, c, got, want)
+    out2 = O.b3_u(u1, u2, u3, mu=2.0, sigma=3.0)
+    assert np.allclose(out2, 2.0 + 3.0 * out.reshape(-1), rtol=0, atol=1e-13)
+
+
+def check_b3_stream():
+    # pair k takes uniforms 3k, 3k + 1, 3k + 2; the stream equals the
+    # explicit-uniform and explicit-word forms; n odd keeps the first value;
+    # restarting at offset + consumed continues it
+    seed, off, n = 0xB3, 77, 30001
+    z, used = O.b3(seed, off, n)
+    P = (n + 1) // 2
+    assert used == 3 * P
+    u = O.uniforms(seed, off, used).reshape(-1, 3)
+    ref = O.b3_u(u[:, 0], u[:, 1], u[:, 2])
+    assert np.array_equal(z, ref[:n])
+    assert np.array_equal(O.b3_words(O.hashes(seed, off, used))[:n], ref[:n])
+    z1, c1 = O.b3(seed, off, 1000)
+    z2, c2 = O.b3(seed, off + c1, n - 1000)
+    assert np.array_equal(np.concatenate([z1, z2]), z) and c1 + c2 == used
+    zs, _ = O.b3(seed, off, n, mu=-1.5, sigma=0.25)
+    assert np.allclose(zs, -1.5 + 0.25 * z, rtol=0, atol=1e-14)
+    # pair by pair against the closed form (the polynomial is within 2e-11
+    # of g), computed here with NumPy's log1p, sin and cos
+    m = np.maximum(u[:, 0], u[:, 1])
+    r = np.sqrt(-2.0 * np.log1p(-(m * m)))
+    t = 2.0 * np.pi * u[:, 2] - np.pi
+    want = np.stack([r * np.cos(t), r * np.sin(t)], axis=1).reshape(-1)[:n]
+    assert np.max(np.abs(z - want) / np.maximum(1.0, np.abs(want))) < 3e-11
+    # and it is not the min(u1, u2) variant or the u3 -> u2 pairing
+    m2 = np.minimum(u[:, 0], u[:, 1])
+    r2 = np.sqrt(-2.0 * np.log1p(-(m2 * m2)))
+    alt = np.stack([r2 * np.cos(t), r2 * np.sin(t)], axis=1).reshape(-1)[:n]
+    assert np.max(np.abs(z - alt)) > 0.1
+
+
+def check_b3_distribution(n: int = 1 << 20):
+    z, _ = O.b3(3, 0, n)
+    _dist_checks(z)
+    from scipy import stats
+    # the angle of (x, y) = r (cos t, sin t) is t = 2 pi u3 - pi
+    ang = (np.arctan2(z[1::2], z[0::2]) / (2 * math.pi)) % 1.0
+    assert stats.kstest(ang, "uniform").statistic < 1.95 / math.sqrt(ang.size)
+    # (x^2 + y^2)/2 = -ln(1 - u) with u = max(u1, u2)^2 uniform
+    e = 0.5 * (z[0::2] ** 2 + z[1::2] ** 2)
+    assert stats.kstest(e, "expon").statistic < 1.95 / math.sqrt(e.size)
+
+
 def check_stats_routines():
     from scipy import special, stats
     g = np.random.Generator(np.random.PCG64(5))
@@ -410,5 +476,5 @@ ALL_CHECKS = [
     check_b1_composition, check_polar_hand, check_polar_lattice, check_polar_composition,
     check_polar_accept_rate, check_polar_s_uniform, check_b1_distribution, check_polar_distribution,
     check_stats_routines, check_p2_poly_bound, check_polar2_hand, check_polar2_lattice, check_polar2_vs_polar,
-    check_polar2_distribution,
+    check_polar2_distribution, check_b3_hand, check_b3_stream, check_b3_distribution,
 ]

@@ -67,6 +67,18 @@ MUTANTS = {
     "p2_consumed": ("            polar2_value(c, X, Y, mu, sigma, &zx, &zy);\n            out[written++] = zx;\n            if (written < n)\n                out[written++] = zy;\n        }\n        ++j;\n    }\n    return 2 * j;",
                     "            polar2_value(c, X, Y, mu, sigma, &zx, &zy);\n            out[written++] = zx;\n            if (written < n)\n                out[written++] = zy;\n        }\n        ++j;\n    }\n    return 2 * j + 2;"),
     "p2_sigma": ("r = sigma * cheb_sum(c, P2_DEGREE, v);", "r = cheb_sum(c, P2_DEGREE, v);"),
+    "b3_min": ("double m = u1 > u2 ? u1 : u2;", "double m = u1 < u2 ? u1 : u2;"),
+    "b3_u_is_m": ("    double u = m * m;\n    double r;\n    if (u > 8.0 / 9.0) {\n        r = sigma * sqrt(-log(1.0 - u));",
+                  "    double u = m;\n    double r;\n    if (u > 8.0 / 9.0) {\n        r = sigma * sqrt(-log(1.0 - u));"),
+    "b3_lib_ln_u": ("r = sigma * sqrt(-log(1.0 - u));", "r = sigma * sqrt(-log(u));"),
+    "b3_drop_m": ("r = sigma * m * cheb_sum(c, P2_DEGREE, v);", "r = sigma * cheb_sum(c, P2_DEGREE, v);"),
+    "b3_angle_shift": ("double t = (2.0 * M_PI) * u3 - M_PI;", "double t = (2.0 * M_PI) * u3;"),
+    "b3_swap_cs": ("*x = cos(t) * rt + mu;\n    *y = sin(t) * rt + mu;", "*x = sin(t) * rt + mu;\n    *y = cos(t) * rt + mu;"),
+    "b3_sqrt2": ("double rt = r * M_SQRT2;\n    *x = cos(t)", "double rt = r;\n    *x = cos(t)"),
+    "b3_threshold": ("    double u = m * m;\n    double r;\n    if (u > 8.0 / 9.0) {", "    double u = m * m;\n    double r;\n    if (u > 0.98) {"),
+    "b3_consumed": ("return 3 * npairs;", "return 2 * npairs;"),
+    "b3_pairing": ("double u3 = orc_uniform(seed, offset + 3 * k + 2);", "double u3 = orc_uniform(seed, offset + 3 * k + 1);"),
+    "b3_words_shift": ("double u3 = (double)(w[3 * p + 2] >> 11) * 0x1p-53;", "double u3 = (double)(w[3 * p + 2] >> 12) * 0x1p-52;"),
     "kurtosis": ("out[3] = m4 / (m2 * m2);", "out[3] = m4 / m2;"),
     "skew": ("out[2] = m3 / (m2 * sqrt(m2));", "out[2] = m3 / m2;"),
     "ks_step": ("double hi = (double)(i + 1) / (double)n - f;", "double hi = (double)i / (double)n - f;"),
