@@ -12,9 +12,9 @@ with every input resident in GPU memory before timing starts.
 Alongside, outside the timed region: the measured store-only and hash-only
 ceilings, the single-stream fills of 2^30 normals (FP32, BF16, FP16 and the
 plain FP64 kernels, the comparison point of the FP32 batched figure), the
-graph-replayed repeated fill (64 x 2^28 Polar normals), method P2 (Section
-4) on the same batched workload, and the CPU oracle timed on the host
-cores.
+graph-replayed repeated fill (64 x 2^28 Polar normals), methods P2 (Section
+4) and B3 (Section 3) on the same batched workload, and the CPU oracle timed
+on the host cores.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extras]
                        [--no-cpu] [--only b1|polar]
@@ -58,14 +58,21 @@ VALU_PEAK_TOPS = 39.32
 #                   and select 2 + the library branch for s > 8/9 (10
 #                   operations, taken by 1/9 of the pairs) 1 + scaling 1 +
 #                   2 conversions and 2 FMAs 4
-ALU_OPS = {"polar_count": 38, "polar_generate": 63, "b1_batched": 67, "p2_count": 37, "p2_generate": 58}
+#   b3_batched:     per pair: hashes of u1 and u2 (18 each) and of u3 (top
+#                   word, 17) + m = max 3 + conversion 3 + u = m^2 1 + v 4 +
+#                   degree-9 Horner 9 + scaling 2 + the library branch's 9
+#                   operations for the 1/9 of pairs above 8/9 1 + split test and
+#                   select 2 + angle reduction, conversion, sin, cos 8 + 2 FMAs
+ALU_OPS = {"polar_count": 38, "polar_generate": 63, "b1_batched": 67, "p2_count": 37, "p2_generate": 58,
+           "b3_batched": 88}
 ALU_UNIT = {"polar_count": "candidate", "polar_generate": "output pair", "b1_batched": "output pair",
-            "p2_count": "candidate", "p2_generate": "output pair"}
+            "p2_count": "candidate", "p2_generate": "output pair", "b3_batched": "output pair"}
 KERNEL_NAMES = {"polar_count": "polar_mask_kernel<MODE_BATCHED> + polar_scan_kernel",
                 "polar_generate": "polar_gen_kernel<float, MODE_BATCHED>",
                 "b1_batched": "b1_batched_kernel<float>",
                 "p2_count": "polar_mask_kernel<MODE_BATCHED, VM_P2> + polar_scan_kernel",
-                "p2_generate": "polar_gen_kernel<float, MODE_BATCHED, VM_P2>"}
+                "p2_generate": "polar_gen_kernel<float, MODE_BATCHED, VM_P2>",
+                "b3_batched": "b1_batched_kernel<float, BM_B3>"}
 PROFILES = os.path.join(ROOT, "profiles")
 
 
@@ -264,21 +271,23 @@ def main() -> int:
     if not args.no_extras:
         result["extras"] = extras(nb, torch, dev, stream, per_kernel, value)
         if args.only != "p2":
-            result["extras"]["p2_batched"] = p2_batched(nb, torch, stream, D, cfg, ns, total, pairs, args.steps,
-                                                        per_kernel)
+            result["extras"]["p2_batched"] = extra_batched(nb, torch, stream, D, ns, total, pairs, args.steps,
+                                                           per_kernel, nb.NRNG_METHOD_P2)
+        result["extras"]["b3_batched"] = extra_batched(nb, torch, stream, D, ns, total, pairs, args.steps,
+                                                       per_kernel, nb.NRNG_METHOD_B3)
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(cfg, [m for m, _ in methods])
     print(json.dumps(result), flush=True)
     return 0
 
 
-def p2_batched(nb, torch, stream, D, cfg, ns, total, pairs, steps, per_kernel):
-    """Method P2 (Section 4) on the same batched workload, timed like the
-    step's Polar leg: plan, then the mask + scan kernels and the generate
-    kernel between events."""
+def extra_batched(nb, torch, stream, D, ns, total, pairs, steps, per_kernel, m):
+    """Method P2 (Section 4) or B3 (Section 3) on the same batched workload,
+    timed like the step's legs: plan, then exec part 1 (P2: the mask and
+    scan kernels; B3: nothing) and part 2 (the generate kernel; the B3
+    kernel) between events."""
     out = torch.empty(total, dtype=torch.float32, device=D["n"].device)
     cons = torch.zeros(ns, dtype=torch.int64, device=D["n"].device)
-    m = nb.NRNG_METHOD_P2
 
     def once(ev=None):
         if ev is not None:
@@ -304,16 +313,22 @@ def p2_batched(nb, torch, stream, D, cfg, ns, total, pairs, steps, per_kernel):
 
     plan_ms, count_ms, gen_ms = avg(0, 1), avg(1, 2), avg(2, 3)
     exec_ms = count_ms + gen_ms
-    cand = int(u64sum(cons)) // 2
-    r = {"plan_ms": round(plan_ms, 5), "count_ms": round(count_ms, 5), "generate_ms": round(gen_ms, 5),
-         "exec_ms": round(exec_ms, 5), "normals_per_s": total / (exec_ms * 1e-3),
-         "write_GBps": round(4.0 * total / (exec_ms * 1e-3) / 1e9, 1), "candidates": cand, "alu": {}}
-    for k, (ms, ops) in {"p2_count": (count_ms, ALU_OPS["p2_count"] * cand),
-                         "p2_generate": (gen_ms, ALU_OPS["p2_generate"] * pairs)}.items():
+    r = {"plan_ms": round(plan_ms, 5), "exec_ms": round(exec_ms, 5), "normals_per_s": total / (exec_ms * 1e-3),
+         "write_GBps": round(4.0 * total / (exec_ms * 1e-3) / 1e9, 1), "alu": {}}
+    if m == nb.NRNG_METHOD_P2:
+        cand = int(u64sum(cons)) // 2
+        r.update({"count_ms": round(count_ms, 5), "generate_ms": round(gen_ms, 5), "candidates": cand})
+        units = {"p2_count": (count_ms, ALU_OPS["p2_count"] * cand),
+                 "p2_generate": (gen_ms, ALU_OPS["p2_generate"] * pairs)}
+    else:
+        r["consumed_uniforms"] = int(u64sum(cons))
+        units = {"b3_batched": (gen_ms, ALU_OPS["b3_batched"] * pairs)}
+    for k, (ms, ops) in units.items():
         r["alu"][k] = {"ms": round(ms, 5), "Tops_per_s": round(ops / (ms * 1e-3) / 1e12, 2),
                        "frac_valu_peak": round(ops / (ms * 1e-3) / 1e12 / VALU_PEAK_TOPS, 4)}
-    if "polar" in per_kernel:
-        r["exec_vs_polar"] = round(per_kernel["polar"]["exec_ms"] / exec_ms, 4)
+    ref = "polar" if m == nb.NRNG_METHOD_P2 else "b1"
+    if ref in per_kernel:
+        r["exec_vs_" + ref] = round(per_kernel[ref]["exec_ms"] / exec_ms, 4)
     return r
 
 
@@ -361,6 +376,8 @@ def extras(nb, torch, dev, stream, per_kernel, batched_value):
         r["polar_write_GBps"] = round(n * nbytes_el / (ms * 1e-3) / 1e9, 1)
         ms = timed(lambda: nb.nrng_polar2(7, 0, n, 0.0, 1.0, out, dt, stream, None), 5)
         r["p2_normals_per_s"] = n / (ms * 1e-3)
+        ms = timed(lambda: nb.nrng_b3(1, 0, n, 0.0, 1.0, out, dt, stream), 5)
+        r["b3_normals_per_s"] = n / (ms * 1e-3)
         single[name] = r
         del out
         torch.cuda.empty_cache()

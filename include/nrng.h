@@ -5,7 +5,8 @@
  * The library turns a counter-based stream of uniform deviates into
  * N(mu, sigma^2) deviates by the two methods of Section 2 of R. P. Brent,
  * "Fast Normal Random Number Generators for Vector Processors" (1993), and
- * by the paper's method P2 (Section 4, see nrng_polar2):
+ * by the paper's methods B3 (Section 3, see nrng_b3) and P2 (Section 4, see
+ * nrng_polar2):
  *
  *   Algorithm B1 (Box-Muller):  r = sigma sqrt(-2 ln(1 - u)),
  *                               x = r sin(2 pi v) + mu,  y = r cos(2 pi v) + mu;
@@ -68,7 +69,7 @@ extern "C" {
 enum nrng_dtype { NRNG_F64 = 0, NRNG_F32 = 1, NRNG_BF16 = 2, NRNG_F16 = 3 };
 
 /* Methods for nrng_batched. */
-enum nrng_method { NRNG_METHOD_B1 = 0, NRNG_METHOD_POLAR = 1, NRNG_METHOD_P2 = 2 };
+enum nrng_method { NRNG_METHOD_B1 = 0, NRNG_METHOD_POLAR = 1, NRNG_METHOD_P2 = 2, NRNG_METHOD_B3 = 3 };
 
 /* Status codes. */
 enum nrng_status {
@@ -110,6 +111,21 @@ int nrng_reserve(uint64_t max_n, uint32_t max_streams);
  * ---------------------------------------------------------------------- */
 int nrng_boxmuller(uint64_t seed, uint64_t offset, uint64_t n, double mu, double sigma, void *out,
                    int dtype, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Method B3 (Section 3), over one stream: Box-Muller with the square root
+ * avoided by drawing two uniforms.  Pair k uses the uniforms u1, u2, u3 of
+ * counters 3k, 3k + 1, 3k + 2 (same uniform definition as B1):
+ *   m = max(u1, u2), u = m^2 (uniform on [0, 1), sqrt(u) = m);
+ *   r = sigma m h(v) with v = (6u - 4)/(4 - 3u) for u <= 8/9 (h: the
+ *   polynomial of nrng_polar2, degree 15 in FP64, 9 in FP32), else
+ *   r = sigma sqrt(-ln(1 - u));
+ *   t = 2 pi u3 - pi; output 2k = mu + cos(t) r sqrt(2), output 2k+1 =
+ *   mu + sin(t) r sqrt(2) (written only if 2k+1 < n).
+ * Consumes exactly 3 ceil(n/2) uniforms.  Arguments, errors and launch
+ * configuration (nrng_tune_set kernel 0) as nrng_boxmuller. */
+int nrng_b3(uint64_t seed, uint64_t offset, uint64_t n, double mu, double sigma, void *out, int dtype,
+            void *stream);
 
 /* ------------------------------------------------------------------------
  * Algorithm P (Polar method), Section 2, over one stream.
@@ -163,7 +179,7 @@ int nrng_polar_dev(uint64_t seed, uint64_t *d_cursor, uint64_t n, double mu, dou
  * Many independent streams in one launch sequence: one small set-up kernel
  * builds the tile table on the device, then one persistent B1 kernel, or
  * the three Polar kernels, cover every stream.
- *   method       NRNG_METHOD_B1, NRNG_METHOD_POLAR or NRNG_METHOD_P2
+ *   method       NRNG_METHOD_B1, NRNG_METHOD_POLAR, NRNG_METHOD_P2 or NRNG_METHOD_B3
  *   nstreams     number of streams (0 is a no-op)
  *   d_seed[j], d_offset[j], d_n[j]  stream j's seed, first counter, length
  *   d_out_off[j] element offset of stream j's output in `out`; NULL means
@@ -173,7 +189,7 @@ int nrng_polar_dev(uint64_t seed, uint64_t *d_cursor, uint64_t n, double mu, dou
  *                range [out_off, out_off + n) does not fit are skipped
  *   d_consumed   optional (may be NULL): d_consumed[j] receives stream j's
  *                consumed uniforms, or UINT64_MAX if the stream was skipped.
- * Stream j's values equal those of nrng_boxmuller / nrng_polar / nrng_polar2 called alone
+ * Stream j's values equal those of nrng_boxmuller / nrng_polar / nrng_polar2 / nrng_b3 called alone
  * with (d_seed[j], d_offset[j], d_n[j], d_mu[j], d_sigma[j]), bit for bit.
  * The total of d_n over valid streams must not exceed out_len; otherwise the
  * device-side check fails the whole call (every d_consumed[j] = UINT64_MAX,
@@ -195,7 +211,7 @@ int nrng_batched(int method, uint32_t nstreams, const uint64_t *d_seed, const ui
  * plan + exec.
  * nrng_batched_exec_part runs one half of exec's launch sequence, for timing
  * and profiling the kernels separately: part 1 = the Polar (or P2) mask and
- * scan kernels (nothing for B1), part 2 = the generate kernel (the B1
+ * scan kernels (nothing for B1 and B3), part 2 = the generate kernel (the B1 or B3
  * kernel for B1), part 0 = both (identical to nrng_batched_exec).  Part 2
  * reads what part 1 of the same plan left in the workspace, so it must
  * follow it on the same stream with no other Polar call in between.  Same
@@ -223,8 +239,8 @@ int nrng_fillgraph_launch(void *graph, void *stream);
 int nrng_fillgraph_destroy(void *graph);
 
 /* ------------------------------------------------------------------------
- * Launch configuration.  kernel: 0 = B1 single stream, 1 = Polar (single,
- * device cursor and batched), 2 = B1 batched.  Sets the workgroup size and
+ * Launch configuration.  kernel: 0 = B1 and B3 single stream, 1 = Polar and
+ * P2 (single, device cursor and batched), 2 = B1 and B3 batched.  Sets the workgroup size and
  * per-thread unroll used for `dtype`; NRNG_EINVAL if that pair is not one of
  * the compiled variants (nrng_tune_variants lists them as (wg, unroll)
  * pairs).  grid_per_cu (0 = from the occupancy query) caps the persistent
@@ -239,6 +255,8 @@ int nrng_tune_variants(int kernel, uint32_t *pairs, int max_pairs);
  *
  * nrng_test_b1_words: pair p uses u-word d_words[2p] and v-word
  *   d_words[2p+1] (64-bit hash words); writes out[2p], out[2p+1].
+ * nrng_test_b3_words: the same for method B3, three words per pair (u1,
+ *   u2, u3), d_words holding 3 npairs words.
  * nrng_test_polar_xy: candidate j is (d_xy[2j], d_xy[2j+1]); accepted
  *   candidates are written compactly in order to out (capacity 2 ncand);
  *   d_mask_words (ceil(ncand/64) words, bit j%64 of word j/64 = accept) and
@@ -254,6 +272,8 @@ int nrng_tune_variants(int kernel, uint32_t *pairs, int max_pairs);
  *   budget.
  * ---------------------------------------------------------------------- */
 int nrng_test_b1_words(const uint64_t *d_words, uint64_t npairs, double mu, double sigma, void *out, int dtype,
+                       void *stream);
+int nrng_test_b3_words(const uint64_t *d_words, uint64_t npairs, double mu, double sigma, void *out, int dtype,
                        void *stream);
 int nrng_test_polar_xy(const int32_t *d_xy, uint64_t ncand, double mu, double sigma, void *out, int dtype,
                        uint64_t *d_mask_words, uint64_t *d_count, void *stream);

@@ -36,7 +36,7 @@ struct DevState {
     uint64_t stream_cap = 0;
     int occ_polar[2][4][4][8] = {};  // generate kernel: [value method][mode][dtype][variant], 0 = not queried
     int occ_mask[2][4][8] = {};      // mask kernel: [value method][mode][variant]
-    int occ_b1[2][4][8] = {};        // [batched][dtype][variant]
+    int occ_b1[2][2][4][8] = {};     // [B1 / B3][batched][dtype][variant]
     // the tile table currently in the workspace (from nrng_batched_plan)
     int plan_method = -1, plan_dtype = -1, plan_vi = -1;
     uint32_t plan_nstreams = 0;
@@ -188,12 +188,12 @@ int polar_mask_blocks_per_cu(DevState &d, int mode, int vm, int vi)
     return o;
 }
 
-int b1_blocks_per_cu(DevState &d, int batched, int dtype, int vi)
+int b1_blocks_per_cu(DevState &d, int batched, int bm, int dtype, int vi)
 {
-    int &o = d.occ_b1[batched][dtype][vi];
+    int &o = d.occ_b1[bm][batched][dtype][vi];
     if (o == 0) {
         int b = 0;
-        if (occupancy_b1(batched, dtype, vi, &b) != (int)hipSuccess || b <= 0)
+        if (occupancy_b1(batched, bm, dtype, vi, &b) != (int)hipSuccess || b <= 0)
             b = 1;
         o = b;
     }
@@ -265,9 +265,71 @@ PolarArgs polar_args(DevState &d)
 // Value method of a batched method id (Polar kernels only).
 int method_vm(int method) { return method == NRNG_METHOD_P2 ? 1 : 0; }
 
+// Box-Muller family (B1, B3): one kernel per tile of pairs, no compaction.
+bool method_bm(int method) { return method == NRNG_METHOD_B1 || method == NRNG_METHOD_B3; }
+
 bool method_ok(int method)
 {
-    return method == NRNG_METHOD_B1 || method == NRNG_METHOD_POLAR || method == NRNG_METHOD_P2;
+    return method == NRNG_METHOD_B1 || method == NRNG_METHOD_POLAR || method == NRNG_METHOD_P2 ||
+           method == NRNG_METHOD_B3;
+}
+
+// B1 (bm 0) or B3 (bm 1) over one stream.
+int bm_single(int bm, uint64_t seed, uint64_t offset, uint64_t n, double mu, double sigma, void *out, int dtype,
+              hipStream_t s)
+{
+    if (!dtype_ok(dtype))
+        return NRNG_EDTYPE;
+    int rc = check_mu_sigma(mu, sigma);
+    if (rc)
+        return rc;
+    if (n == 0)
+        return NRNG_OK;
+    if (!out)
+        return NRNG_EINVAL;
+    if (n > (1ull << 62))
+        return NRNG_ERANGE;
+    std::lock_guard<std::mutex> lk(g_mu);
+    DevState *d;
+    if ((rc = get_dev(&d)))
+        return rc;
+    const Tune tu = g_tune[0][dtype];
+    const Variant *v;
+    b1_variants(&v);
+    const uint64_t ppl = (dtype == NRNG_F64) ? 1 : (dtype == NRNG_F32 ? 2 : 4);
+    const uint64_t nchunks = ((n + 1) / 2 + ppl - 1) / ppl;
+    const uint64_t blocks = (nchunks + (uint64_t)v[tu.vi].wg * v[tu.vi].unroll - 1) /
+                            ((uint64_t)v[tu.vi].wg * v[tu.vi].unroll);
+    const uint32_t grid = persistent_grid(*d, b1_blocks_per_cu(*d, 0, bm, dtype, tu.vi), tu.grid_per_cu, blocks);
+    B1Args a;
+    std::memset(&a, 0, sizeof(a));
+    a.ctr0 = seed + offset;
+    a.n = n;
+    a.mu = mu;
+    a.sigma = sigma;
+    a.out = out;
+    return hip_status(launch_b1_single(bm, dtype, tu.vi, a, grid, s));
+}
+
+int bm_words(int bm, const uint64_t *d_words, uint64_t npairs, double mu, double sigma, void *out, int dtype,
+             hipStream_t s)
+{
+    if (!dtype_ok(dtype))
+        return NRNG_EDTYPE;
+    int rc = check_mu_sigma(mu, sigma);
+    if (rc)
+        return rc;
+    if (npairs == 0)
+        return NRNG_OK;
+    if (!d_words || !out)
+        return NRNG_EINVAL;
+    B1Args a;
+    std::memset(&a, 0, sizeof(a));
+    a.mu = mu;
+    a.sigma = sigma;
+    a.out = out;
+    a.words = d_words;
+    return hip_status(launch_b1_words(bm, dtype, a, npairs, s));
 }
 
 // Single-stream Polar or P2 (also the device-cursor form): `words` is the
@@ -426,37 +488,12 @@ int nrng_reserve(uint64_t max_n, uint32_t max_streams)
 int nrng_boxmuller(uint64_t seed, uint64_t offset, uint64_t n, double mu, double sigma, void *out, int dtype,
                    void *stream)
 {
-    if (!dtype_ok(dtype))
-        return NRNG_EDTYPE;
-    int rc = check_mu_sigma(mu, sigma);
-    if (rc)
-        return rc;
-    if (n == 0)
-        return NRNG_OK;
-    if (!out)
-        return NRNG_EINVAL;
-    if (n > (1ull << 62))
-        return NRNG_ERANGE;
-    std::lock_guard<std::mutex> lk(g_mu);
-    DevState *d;
-    if ((rc = get_dev(&d)))
-        return rc;
-    const Tune tu = g_tune[0][dtype];
-    const Variant *v;
-    b1_variants(&v);
-    const uint64_t ppl = (dtype == NRNG_F64) ? 1 : (dtype == NRNG_F32 ? 2 : 4);
-    const uint64_t nchunks = ((n + 1) / 2 + ppl - 1) / ppl;
-    const uint64_t blocks = (nchunks + (uint64_t)v[tu.vi].wg * v[tu.vi].unroll - 1) /
-                            ((uint64_t)v[tu.vi].wg * v[tu.vi].unroll);
-    const uint32_t grid = persistent_grid(*d, b1_blocks_per_cu(*d, 0, dtype, tu.vi), tu.grid_per_cu, blocks);
-    B1Args a;
-    std::memset(&a, 0, sizeof(a));
-    a.ctr0 = seed + offset;
-    a.n = n;
-    a.mu = mu;
-    a.sigma = sigma;
-    a.out = out;
-    return hip_status(launch_b1_single(dtype, tu.vi, a, grid, S(stream)));
+    return bm_single(0, seed, offset, n, mu, sigma, out, dtype, S(stream));
+}
+
+int nrng_b3(uint64_t seed, uint64_t offset, uint64_t n, double mu, double sigma, void *out, int dtype, void *stream)
+{
+    return bm_single(1, seed, offset, n, mu, sigma, out, dtype, S(stream));
 }
 
 int nrng_polar(uint64_t seed, uint64_t offset, uint64_t n, double mu, double sigma, void *out, int dtype,
@@ -508,7 +545,7 @@ int nrng_batched_plan(int method, uint32_t nstreams, const uint64_t *d_n, const 
         return rc;
     if ((rc = ensure_streams(*d, nstreams, s)))
         return rc;
-    const int kid = method == NRNG_METHOD_B1 ? 2 : 1;
+    const int kid = method_bm(method) ? 2 : 1;
     const Tune tu = g_tune[kid][dtype];
     PrepArgs p;
     std::memset(&p, 0, sizeof(p));
@@ -520,7 +557,7 @@ int nrng_batched_plan(int method, uint32_t nstreams, const uint64_t *d_n, const 
     p.tile_start = d->tile_start;
     p.packed_off = d->packed_off;
     p.consumed = d_consumed;
-    if (method == NRNG_METHOD_B1) {
+    if (method_bm(method)) {
         const Variant *v;
         b1_variants(&v);
         const uint64_t ppl = (dtype == NRNG_F64) ? 1 : (dtype == NRNG_F32 ? 2 : 4);
@@ -580,7 +617,7 @@ int nrng_batched_exec_part(int part, int method, uint32_t nstreams, const uint64
         return rc;
     // the tile table must come from a plan for this method, dtype, variant,
     // stream count and layout
-    const int kid = method == NRNG_METHOD_B1 ? 2 : 1;
+    const int kid = method_bm(method) ? 2 : 1;
     const Tune tu = g_tune[kid][dtype];
     if (d->plan_method != method || d->plan_dtype != dtype || d->plan_vi != tu.vi ||
         d->plan_nstreams != nstreams || d->plan_packed != (d_out_off == nullptr))
@@ -588,7 +625,7 @@ int nrng_batched_exec_part(int part, int method, uint32_t nstreams, const uint64
     if (!out)
         return NRNG_EINVAL;
     const uint64_t *off = d_out_off ? d_out_off : d->packed_off;
-    if (method == NRNG_METHOD_B1) {
+    if (method_bm(method)) {
         B1Args a;
         std::memset(&a, 0, sizeof(a));
         a.out = out;
@@ -601,9 +638,10 @@ int nrng_batched_exec_part(int part, int method, uint32_t nstreams, const uint64
         a.mus = d_mu;
         a.sigmas = d_sigma;
         if (part == 1)
-            return NRNG_OK;   // B1 has no count pass
-        const uint32_t grid = persistent_grid(*d, b1_blocks_per_cu(*d, 1, dtype, tu.vi), tu.grid_per_cu, 0);
-        return hip_status(launch_b1_batched(dtype, tu.vi, a, grid, s));
+            return NRNG_OK;   // B1 and B3 have no count pass
+        const int bm = method == NRNG_METHOD_B3 ? 1 : 0;
+        const uint32_t grid = persistent_grid(*d, b1_blocks_per_cu(*d, 1, bm, dtype, tu.vi), tu.grid_per_cu, 0);
+        return hip_status(launch_b1_batched(bm, dtype, tu.vi, a, grid, s));
     }
     PolarArgs a = polar_args(*d);
     a.mu = 0.0;
@@ -768,22 +806,13 @@ int nrng_tune_variants(int kernel, uint32_t *pairs, int max_pairs)
 int nrng_test_b1_words(const uint64_t *d_words, uint64_t npairs, double mu, double sigma, void *out, int dtype,
                        void *stream)
 {
-    if (!dtype_ok(dtype))
-        return NRNG_EDTYPE;
-    int rc = check_mu_sigma(mu, sigma);
-    if (rc)
-        return rc;
-    if (npairs == 0)
-        return NRNG_OK;
-    if (!d_words || !out)
-        return NRNG_EINVAL;
-    B1Args a;
-    std::memset(&a, 0, sizeof(a));
-    a.mu = mu;
-    a.sigma = sigma;
-    a.out = out;
-    a.words = d_words;
-    return hip_status(launch_b1_words(dtype, a, npairs, S(stream)));
+    return bm_words(0, d_words, npairs, mu, sigma, out, dtype, S(stream));
+}
+
+int nrng_test_b3_words(const uint64_t *d_words, uint64_t npairs, double mu, double sigma, void *out, int dtype,
+                       void *stream)
+{
+    return bm_words(1, d_words, npairs, mu, sigma, out, dtype, S(stream));
 }
 
 int nrng_test_polar_xy(const int32_t *d_xy, uint64_t ncand, double mu, double sigma, void *out, int dtype,

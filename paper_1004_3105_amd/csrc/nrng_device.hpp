@@ -1,8 +1,9 @@
 // nrng_device.hpp -- device-side building blocks of the normal-deviate
 // kernels for gfx950: the counter-based uniform source, the per-pair
 // transforms of Box-Muller (Algorithm B1) and the Polar method (Algorithm P)
-// [Brent 1993, Section 2] and of method P2 (Section 4), output conversion
-// and store helpers, and the wavefront primitives of the Polar compaction.
+// [Brent 1993, Section 2] and of methods B3 (Section 3) and P2 (Section 4),
+// output conversion and store helpers, and the wavefront primitives of the
+// Polar compaction.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -150,19 +151,23 @@ __device__ __forceinline__ float u64_to_f32_scaled(uint64_t q, float scale_hi, f
 // y = r cos(2 pi v) + mu, with u = (ku >> 11) 2^-53 and v = (kv >> 11) 2^-53.
 // ---------------------------------------------------------------------------
 
-// FP64 evaluation, in the order of the algorithm with no fused operations:
-// 1 - u is exact, the angle is the rounded product (2 pi) v.
+// FP64 evaluation, in the order of the algorithm with no fused operations
+// (contraction is switched off in each FP64 evaluation below): 1 - u is
+// exact, the angle is the rounded product (2 pi) v.
 __device__ __forceinline__ void b1_pair_f64(uint64_t ku, uint64_t kv, double mu, double sigma, double& x,
                                             double& y)
 {
+    // one rounding per operation, as written (the compiler would otherwise
+    // fuse a product and a following sum into an FMA)
+#pragma clang fp contract(off)
     double u = (double)(ku >> 11) * 0x1p-53;
     double v = (double)(kv >> 11) * 0x1p-53;
-    double r = __dmul_rn(sigma, sqrt(__dmul_rn(-2.0, log(__dsub_rn(1.0, u)))));
-    double t = __dmul_rn(2.0 * 3.141592653589793115997963, v);   // 2 fl(pi), exact doubling
+    double r = sigma * sqrt(-2.0 * log(1.0 - u));
+    double t = (2.0 * 3.141592653589793115997963) * v;   // 2 fl(pi), exact doubling
     double s, c;
     sincos(t, &s, &c);
-    x = __dadd_rn(__dmul_rn(r, s), mu);
-    y = __dadd_rn(__dmul_rn(r, c), mu);
+    x = r * s + mu;
+    y = r * c + mu;
 }
 
 // FP32 evaluation.
@@ -224,14 +229,18 @@ __device__ __forceinline__ bool polar_accept(uint64_t S)
     return S - 1 < (1ull << 62) - 1;
 }
 
-// FP64 value: s = RNE(S) 2^-62, r = sigma sqrt(-2 ln(s) / s), no fused ops.
+// FP64 value: s = RNE(S) 2^-62, r = sigma sqrt(-2 ln(s) / s), no fused
+// operations.
 __device__ __forceinline__ void polar_value_f64(int32_t X, int32_t Y, uint64_t S, double mu, double sigma,
                                                 double& zx, double& zy)
 {
-    double s = __dmul_rn((double)S, 0x1p-62);
-    double r = __dmul_rn(sigma, sqrt(__ddiv_rn(__dmul_rn(-2.0, log(s)), s)));
-    zx = __dadd_rn(__dmul_rn(r, __dmul_rn((double)X, 0x1p-31)), mu);
-    zy = __dadd_rn(__dmul_rn(r, __dmul_rn((double)Y, 0x1p-31)), mu);
+    // one rounding per operation, as written (the compiler would otherwise
+    // fuse a product and a following sum into an FMA)
+#pragma clang fp contract(off)
+    double s = (double)S * 0x1p-62;
+    double r = sigma * sqrt(-2.0 * log(s) / s);
+    zx = r * ((double)X * 0x1p-31) + mu;
+    zy = r * ((double)Y * 0x1p-31) + mu;
 }
 
 // FP32 value.
@@ -306,11 +315,114 @@ __device__ __forceinline__ void polar_value_f32(int32_t X, int32_t Y, uint64_t S
 // instruction because the compiler otherwise turns a select between two
 // costly values into a branch around each, which serialises the pairs a lane
 // computes (in a wave of 64 lanes both sides are almost always needed).
+// The leading s_nop supplies the wait states that gfx950 requires between a
+// transcendental instruction (v_sqrt_f32 and the like) and a VALU
+// instruction reading its result: the compiler inserts them for its own
+// instructions but not ahead of an inline-assembly reader, which would
+// otherwise see the register's previous value.
 __device__ __forceinline__ float select_lanes(uint64_t m, float a, float b)
 {
     float r;
-    asm("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(m));
+    asm("s_nop 1\n\tv_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(m));
     return r;
+}
+
+// ---------------------------------------------------------------------------
+// Method B3 (Section 3).  Per pair three uniforms u1, u2, u3 (counters c,
+// c + 1, c + 2): m = max(u1, u2) and u = m^2 (uniform, with sqrt(u) = m);
+// r = sigma m h(v), v = (6u - 4)/(4 - 3u), for u <= 8/9, else
+// r = sigma sqrt(-ln(1 - u)); t = 2 pi u3 - pi; outputs mu + cos(t) r sqrt(2)
+// then mu + sin(t) r sqrt(2).  h is the polynomial of method P2.
+// ---------------------------------------------------------------------------
+
+// u > 8/9 with u = RNE_double(m * m), m = mk 2^-53, as the integer test
+// mk > kB3SplitM (RNE rounding is monotone, so the set is a ray).  The
+// largest mk whose rounded square does not exceed the double 8/9 is found by
+// bisection at compile time, with the same double products.
+constexpr uint64_t b3_split_m()
+{
+    uint64_t lo = 0, hi = 1ull << 53;
+    while (hi - lo > 1) {
+        const uint64_t mid = lo + (hi - lo) / 2;
+        const double m = (double)mid * 0x1p-53;
+        if (m * m <= 8.0 / 9.0)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+constexpr uint64_t kB3SplitM = b3_split_m();
+
+// FP64, in the order of the steps with no fused operations except in the
+// polynomial (Horner's rule with FMA).
+__device__ __forceinline__ void b3_pair_f64(uint64_t k1, uint64_t k2, uint64_t k3, double mu, double sigma,
+                                            double& x, double& y)
+{
+    // one rounding per operation, as written (the compiler would otherwise
+    // fuse a product and a following sum into an FMA)
+#pragma clang fp contract(off)
+    const double u1 = (double)(k1 >> 11) * 0x1p-53;
+    const double u2 = (double)(k2 >> 11) * 0x1p-53;
+    const double u3 = (double)(k3 >> 11) * 0x1p-53;
+    const double m = u1 > u2 ? u1 : u2;
+    const double u = m * m;
+    double r;
+    if (u > 8.0 / 9.0) {
+        r = sigma * sqrt(-log(1.0 - u));
+    } else {
+        const double v = (6.0 * u - 4.0) / (4.0 - 3.0 * u);
+        double h = kP2PolyF64[kP2PolyF64Deg];
+#pragma unroll
+        for (int k = kP2PolyF64Deg - 1; k >= 0; --k)
+            h = __builtin_fma(h, v, kP2PolyF64[k]);
+        r = sigma * m * h;
+    }
+    const double t = (2.0 * 3.141592653589793115997963) * u3 - 3.141592653589793115997963;
+    double sn, cs;
+    sincos(t, &sn, &cs);
+    const double rt = r * 1.4142135623730951;
+    x = cs * rt + mu;
+    y = sn * rt + mu;
+}
+
+// FP32.  ks = sigma sqrt(2), k2 = -2 ln 2 sigma^2.
+//  * m from the larger 53-bit integer, rounded once.
+//  * u <= 8/9: r sqrt(2) = ks m h(v), v by one reciprocal, h of degree 9.
+//  * u > 8/9: 1 - u = (1 - m)(1 + m) with 1 - m = (2^53 - mk) 2^-53 exact
+//    before its one rounding, so -ln(1 - u) keeps its relative accuracy;
+//    r sqrt(2) = sqrt(log2(1 - u) k2).  Both branches are formed and one is
+//    selected.
+//  * The angle: u3 - 1/2 is the top word of u3's hash read as a signed
+//    fraction of a turn (exact); when it exceeds a quarter turn in magnitude,
+//    half a turn is added and r negated, so the float angle has absolute
+//    error at most 2^-27 turns.  v_sin_f32 / v_cos_f32 take revolutions.
+__device__ __forceinline__ void b3_pair_f32(uint64_t k1, uint64_t k2, uint32_t k3_hi, float mu, float ks, float k2c,
+                                            float& x, float& y)
+{
+    const uint64_t a1 = k1 >> 11, a2 = k2 >> 11;
+    const uint64_t mk = a1 > a2 ? a1 : a2;
+    const float mf = u64_to_f32_scaled(mk, 0x1p-21f, 0x1p-53f);
+    const float uf = mf * mf;
+    const float num = __builtin_fmaf(uf, 6.0f, -4.0f);
+    const float den = __builtin_fmaf(uf, -3.0f, 4.0f);
+    const float v = num * __builtin_amdgcn_rcpf(den);
+    float h = kP2PolyF32[kP2PolyF32Deg];
+#pragma unroll
+    for (int k = kP2PolyF32Deg - 1; k >= 0; --k)
+        h = __builtin_fmaf(h, v, kP2PolyF32[k]);
+    const float rp = h * mf * ks;
+    const float dm = u64_to_f32_scaled((1ull << 53) - mk, 0x1p-21f, 0x1p-53f);   // 1 - m
+    const float rl = __builtin_amdgcn_sqrtf(__builtin_amdgcn_logf(dm * (1.0f + mf)) * k2c);
+    float r = select_lanes(__ballot(mk > kB3SplitM), rp, rl);
+
+    const uint32_t a = k3_hi ^ 0x80000000u;               // (u3 - 1/2) 2^32, as int32
+    const bool flip = (a + 0x40000000u) >= 0x80000000u;
+    const int32_t af = (int32_t)(flip ? (a ^ 0x80000000u) : a);
+    r = flip ? -r : r;
+    const float turns = (float)af * 0x1p-32f;
+    x = __builtin_fmaf(r, __builtin_amdgcn_cosf(turns), mu);
+    y = __builtin_fmaf(r, __builtin_amdgcn_sinf(turns), mu);
 }
 
 // ---------------------------------------------------------------------------
@@ -333,25 +445,28 @@ constexpr uint64_t kP2SplitS = kP2TauS + 256 - ((kP2TauS >> 9) & 1);
 __device__ __forceinline__ bool polar2_big(uint64_t S) { return S > kP2SplitS; }
 
 // FP64 value, in the order of the steps with no fused operations except in
-// the polynomial (Horner's rule with FMA).
+// the polynomial (Horner's rule with explicit FMA).
 __device__ __forceinline__ void polar2_value_f64(int32_t X, int32_t Y, uint64_t S, double mu, double sigma,
                                                  double& zx, double& zy)
 {
-    const double s = __dmul_rn((double)S, 0x1p-62);
+    // one rounding per operation, as written (the compiler would otherwise
+    // fuse a product and a following sum into an FMA)
+#pragma clang fp contract(off)
+    const double s = (double)S * 0x1p-62;
     double r;
     if (s > 8.0 / 9.0) {
-        r = __dmul_rn(sigma, sqrt(__ddiv_rn(-log(__dsub_rn(1.0, s)), s)));
+        r = sigma * sqrt(-log(1.0 - s) / s);
     } else {
-        const double v = __ddiv_rn(__dsub_rn(__dmul_rn(6.0, s), 4.0), __dsub_rn(4.0, __dmul_rn(3.0, s)));
+        const double v = (6.0 * s - 4.0) / (4.0 - 3.0 * s);
         double h = kP2PolyF64[kP2PolyF64Deg];
 #pragma unroll
         for (int k = kP2PolyF64Deg - 1; k >= 0; --k)
             h = __builtin_fma(h, v, kP2PolyF64[k]);
-        r = __dmul_rn(sigma, h);
+        r = sigma * h;
     }
-    const double rt = __dmul_rn(r, 1.4142135623730951);   // sqrt(2) rounded to double
-    zx = __dadd_rn(__dmul_rn(rt, __dmul_rn((double)X, 0x1p-31)), mu);
-    zy = __dadd_rn(__dmul_rn(rt, __dmul_rn((double)Y, 0x1p-31)), mu);
+    const double rt = r * 1.4142135623730951;   // sqrt(2) rounded to double
+    zx = rt * ((double)X * 0x1p-31) + mu;
+    zy = rt * ((double)Y * 0x1p-31) + mu;
 }
 
 // FP32 radius factor times 2^-31: sigma sqrt(2) g(s) 2^-31.  ks31 =

@@ -62,7 +62,7 @@ struct B1Args {
     uint64_t n;
     double mu, sigma;
     void *out;
-    const uint64_t *words;   // explicit hash words (test hook) or null
+    const uint64_t *words;   // explicit hash words (test hook; 2 per pair for B1, 3 for B3) or null
     // batched
     uint32_t nstreams;
     const uint64_t *tile_start;
@@ -71,11 +71,11 @@ struct B1Args {
 };
 
 struct PrepArgs {
-    int method;
+    int method;                      // 0 = B1, 1 = Polar, 2 = P2, 3 = B3
     uint32_t nstreams;
     const uint64_t *ns, *out_off;    // out_off nullable (packed)
     uint64_t out_len;
-    uint64_t unit;                   // B1: pairs per tile; Polar: mask words per tile
+    uint64_t unit;                   // B1, B3: pairs per tile; Polar, P2: mask words per tile
     uint64_t word_cap;               // Polar: workspace capacity in mask words (tiles x unit)
     uint64_t tile_cap;               // Polar: workspace capacity in tiles
     uint64_t *tile_start;            // out: nstreams + 1
@@ -90,9 +90,10 @@ int b1_variants(const Variant **v);
 int polar_variants(const Variant **v);
 
 // Launchers (return hipError_t as int).  `vi` indexes the variant table.
-int launch_b1_single(int dtype, int vi, const B1Args &a, uint32_t grid, hipStream_t s);
-int launch_b1_words(int dtype, const B1Args &a, uint64_t npairs, hipStream_t s);
-int launch_b1_batched(int dtype, int vi, const B1Args &a, uint32_t grid, hipStream_t s);
+// B1 family: bm 0 = Algorithm B1, 1 = method B3.
+int launch_b1_single(int bm, int dtype, int vi, const B1Args &a, uint32_t grid, hipStream_t s);
+int launch_b1_words(int bm, int dtype, const B1Args &a, uint64_t npairs, hipStream_t s);
+int launch_b1_batched(int bm, int dtype, int vi, const B1Args &a, uint32_t grid, hipStream_t s);
 // Polar: the mask, scan and generate kernels, in that order on stream s.
 // vm selects the value method: 0 = Algorithm P, 1 = method P2 (no trace
 // mode).  grid_mask / grid_gen are the persistent grid sizes of the first and
@@ -103,7 +104,7 @@ int launch_polar(int mode, int vm, int dtype, int vi, const PolarArgs &a, uint32
 int launch_prep(const PrepArgs &a, hipStream_t s);
 int occupancy_polar(int mode, int vm, int dtype, int vi, int *blocks_per_cu);        // generate kernel
 int occupancy_polar_mask(int mode, int vm, int vi, int *blocks_per_cu);
-int occupancy_b1(int batched, int dtype, int vi, int *blocks_per_cu);
+int occupancy_b1(int batched, int bm, int dtype, int vi, int *blocks_per_cu);
 int launch_probe_store(void *out, uint64_t nbytes, uint32_t grid, hipStream_t s);
 int launch_probe_copy(void *dst, const void *src, uint64_t nbytes, uint32_t grid, hipStream_t s);
 int launch_probe_hash(uint64_t seed, uint64_t nhash, uint64_t *sink, uint64_t sink_len, uint32_t grid,

@@ -103,6 +103,34 @@ def polar_edge_xy(seed: int = 13) -> np.ndarray:
     return allp.astype(np.int32).reshape(-1)
 
 
+def b3_edge_words(seed: int = 15) -> np.ndarray:
+    """Explicit 64-bit hash words for the B3 test hook, three per pair
+    (u1, u2, u3 words; u = (w >> 11) 2^-53): the hand-value uniforms,
+    m = max(u1, u2) within a few units (of 2^-53) of the split u = m^2 = 8/9
+    on both sides, m = 0 and m = 1 - 2^-53, angles at every eighth of a turn,
+    and random words."""
+    g = rng(seed)
+
+    def w(u):   # a word whose top 53 bits are u 2^53 (u a multiple of 2^-53)
+        return np.uint64(int(round(u * 2.0**53)) << 11)
+
+    rows = []
+    for u1, u2, u3 in ((0.5, 0.25, 0.5), (0.25, 0.5, 0.5), (0.25, 0.5, 0.75), (0.5, 0.25, 0.0),
+                       (0.5, 0.5, 0.625), (0.5, 0.5, 0.875), (0.9375, 0.5, 0.5), (0.5, 0.9453125, 0.5),
+                       (0.96875, 0.1, 0.5), (0.0, 0.0, 0.3), (1 - 2.0**-53, 0.3, 0.5)):
+        rows.append((w(u1), w(u2), w(u3)))
+    split = math.isqrt(int(8 * 2**106 // 9))          # about sqrt(8/9) 2^53
+    for d in range(-4, 5):
+        mk = split + d
+        rows.append((np.uint64(mk << 11), np.uint64(int(g.integers(0, mk)) << 11), w(0.3)))
+        rows.append((np.uint64(int(g.integers(0, mk)) << 11), np.uint64(mk << 11), w(0.7)))
+    for e in range(16):
+        rows.append((w(0.6), w(0.2), w(e / 16)))
+    arr = np.array(rows, dtype=np.uint64).reshape(-1)
+    rnd = g.integers(0, 2**64, 3 * 8192, dtype=np.uint64, endpoint=False)
+    return np.concatenate([arr, rnd])
+
+
 def polar2_edge_xy(seed: int = 14) -> np.ndarray:
     """Explicit int32 candidate pairs for the P2 test hook: the Polar edge
     points (which include the origin, accepted by P2), the origin repeated

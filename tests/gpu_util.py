@@ -8,7 +8,7 @@ import numpy as np
 import torch
 
 from paper_1004_3105_amd import binding as nb
-from helpers import fp32_tol, fp64_p2_tol, fp64_scaled_tol, half_tol, ulp_dist64_fast
+from helpers import fp32_tol, fp64_poly_tol, fp64_scaled_tol, half_tol, ulp_dist64_fast
 
 TDT = {nb.NRNG_F64: torch.float64, nb.NRNG_F32: torch.float32, nb.NRNG_BF16: torch.bfloat16,
        nb.NRNG_F16: torch.float16}
@@ -35,6 +35,8 @@ def run(method: str, seed: int, offset: int, n: int, dtype: int, mu: float = 0.0
     case(method, NAME[dtype], "seed", seed, "offset", offset, "n", n, "mu", mu, "sigma", sigma)
     if method == "b1":
         nb.nrng_boxmuller(seed, offset, n, mu, sigma, out, dtype)
+    elif method == "b3":
+        nb.nrng_b3(seed, offset, n, mu, sigma, out, dtype)
     elif method == "polar2":
         nb.nrng_polar2(seed, offset, n, mu, sigma, out, dtype, None, cons)
     else:
@@ -54,16 +56,17 @@ def u64(t: torch.Tensor) -> np.ndarray:
 
 
 def assert_close(z: np.ndarray, ref: np.ndarray, dtype: int, mu=0.0, sigma=1.0, what: str = "",
-                 p2: bool = False):
-    """Compare GPU values with the oracle's at the bar of the dtype (p2: the
-    FP64 bar of method P2, see helpers.fp64_p2_tol).  Returns the largest ulp
+                 poly: bool = False):
+    """Compare GPU values with the oracle's at the bar of the dtype (poly: the
+    FP64 bar of the methods with the Section 3 polynomial, P2 and B3; see
+    helpers.fp64_poly_tol).  Returns the largest ulp
     distance (FP64) or the largest fraction of the bar (other dtypes)."""
     assert z.shape == ref.shape, (z.shape, ref.shape)
     if dtype == nb.NRNG_F64:
         d = ulp_dist64_fast(z, ref)
         ok = d <= 4
-        if p2:
-            ok |= np.abs(z - ref) <= fp64_p2_tol(ref, mu, sigma)
+        if poly:
+            ok |= np.abs(z - ref) <= fp64_poly_tol(ref, mu, sigma)
         if np.any(mu != 0.0):
             # z = sigma n + mu: four units in the last place of the larger of
             # |z|, |mu| and sigma |n| (for mu = 0 this is the plain 4-ulp bar)

@@ -76,9 +76,9 @@ def fp64_scaled_tol(z_ref: np.ndarray, mu, sigma) -> np.ndarray:
     return 4.0 * np.spacing(scale)
 
 
-def fp64_p2_tol(z_ref: np.ndarray, mu, sigma) -> np.ndarray:
-    """FP64 bar for method P2: the 4-ulp bar of fp64_scaled_tol plus
-    4e-15 sigma |n|.  The two sides evaluate the same degree-15 polynomial
+def fp64_poly_tol(z_ref: np.ndarray, mu, sigma) -> np.ndarray:
+    """FP64 bar for the methods that evaluate the Section 3 polynomial (P2
+    and B3): the 4-ulp bar of fp64_scaled_tol plus 4e-15 sigma |n|.  The two sides evaluate the same degree-15 polynomial
     h(v) differently: the oracle sums the Chebyshev series by the three-term
     recurrence (measured error up to 6.7e-16 against 40-digit evaluation),
     the kernel uses Horner's rule on the monomial coefficients (2.2e-16);

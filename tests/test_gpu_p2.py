@@ -4,7 +4,7 @@ polynomial in v = (6s - 4)/(4 - 3s) for s <= 8/9) against the FP64 oracle,
 through the C ABI.
 
 Bars: accept masks, output indices and consumed counts bit-exact; FP64
-within 4 ulp plus 4e-15 sigma |n| (helpers.fp64_p2_tol: the two sides
+within 4 ulp plus 4e-15 sigma |n| (helpers.fp64_poly_tol: the two sides
 evaluate the degree-15 polynomial by different schemes); FP32 within
 2e-6 max(1, |z|) (widened by |mu| and sigma |n| when mu != 0); BF16/FP16
 within one unit of the format plus the FP32 bar."""
@@ -28,7 +28,7 @@ def test_p2_f64_stream():
     ref, used = O.polar2(7, 0, n)
     zt, cons = run("polar2", 7, 0, n, nb.NRNG_F64, with_consumed=True)
     assert cons == used
-    assert_close(host(zt), ref, nb.NRNG_F64, what="p2 f64", p2=True)
+    assert_close(host(zt), ref, nb.NRNG_F64, what="p2 f64", poly=True)
 
 
 @pytest.mark.parametrize("seed,offset,mu,sigma", [(7, 0, 0.0, 1.0), (0xC0FFEE, 999, -4.0, 3.0)])
@@ -69,7 +69,7 @@ def test_p2_xy_edge_cases(dtype):
     torch.cuda.synchronize()
     assert np.array_equal(u64(gm), masks)
     assert int(cnt.item()) == a
-    assert_close(host(out[:2 * a]), ref, dtype, what="p2 xy", p2=True)
+    assert_close(host(out[:2 * a]), ref, dtype, what="p2 xy", poly=True)
 
 
 def test_p2_hand_values_through_gpu():
@@ -154,7 +154,7 @@ def test_p2_batched_matches_oracle():
             mu, sg = float(cfg["mu"][j]), float(cfg["sigma"][j])
             ref, used = O.polar2(int(cfg["seed"][j]), int(cfg["offset"][j]), n, mu, sg)
             assert int(c[j]) == used, j
-            assert_close(z[o0:o0 + n], ref, dtype, mu, sg, what="p2 batched stream %d" % j, p2=True)
+            assert_close(z[o0:o0 + n], ref, dtype, mu, sg, what="p2 batched stream %d" % j, poly=True)
 
 
 def test_p2_results_do_not_depend_on_launch_variant():
@@ -196,7 +196,7 @@ def test_p2_error_report(capsys):
     rows = []
     for dtype in FLOAT_DTYPES:
         z = host(run("polar2", 7, 0, n, dtype))
-        frac = assert_close(z, ref, dtype, what="p2 %s" % NAME[dtype], p2=True)
+        frac = assert_close(z, ref, dtype, what="p2 %s" % NAME[dtype], poly=True)
         rel = float(np.max(np.abs(z - ref) / np.maximum(1.0, np.abs(ref))))
         rows.append("p2 %-4s max|dz|/max(1,|z|) %.3e  %s" % (
             NAME[dtype], rel, ("max ulp %d" % frac) if dtype == nb.NRNG_F64 else ("max err/bar %.3f" % frac)))
