@@ -4,8 +4,8 @@ This package wraps ``nrng_oracle.c`` -- a plain single-threaded C99
 implementation, in IEEE double precision without fused multiply-add, of
 Box-Muller Algorithm B1 and the Polar method (Algorithm P) from Section 2 of
 Brent's "Fast Normal Random Number Generators for Vector Processors" (1993),
-method B3 of its Section 3 and method P2 of its Section 4, fed by a
-counter-based SplitMix64 uniform stream.
+method B3 of its Section 3, method P2 of its Section 4 and Algorithm R of
+its Section 5, fed by a counter-based SplitMix64 uniform stream.
 
 Only the test suite, the smoke check and the CPU-baseline leg of the
 benchmark may import it.  The product library (``paper_1004_3105_amd``)
@@ -80,6 +80,12 @@ def lib():
                 "orc_b3_u": (None, [vp, vp, vp, u64, f64, f64, vp]),
                 "orc_b3_words": (None, [vp, u64, f64, f64, vp]),
                 "orc_b3": (u64, [u64, u64, u64, f64, f64, vp]),
+                "orc_ratio_accept": (ctypes.c_int, [f64, f64]),
+                "orc_ratio_words": (u64, [vp, u64, f64, f64, vp, vp]),
+                "orc_ratio": (u64, [u64, u64, u64, f64, f64, vp]),
+                "orc_ratio_count": (u64, [u64, u64, u64]),
+                "orc_ratio_trace": (u64, [u64, u64, u64, vp, vp]),
+                "orc_ratio_window": (u64, [u64, u64, u64, u64, f64, f64, vp]),
                 "orc_moments": (None, [vp, u64, vp]),
                 "orc_normal_cdf": (f64, [f64]),
                 "orc_ks": (f64, [vp, u64, ctypes.c_int, f64, f64]),
@@ -338,6 +344,47 @@ def b3_words(words, mu: float = 0.0, sigma: float = 1.0) -> np.ndarray:
     out = np.empty(2 * (w.size // 3), dtype=np.float64)
     lib().orc_b3_words(_p(w), w.size // 3, mu, sigma, _p(out))
     return out
+
+
+# ---------------------------------------------------------------- Algorithm R
+def ratio(seed: int, offset: int, n: int, mu: float = 0.0, sigma: float = 1.0):
+    """n normals by Algorithm R; returns (values, uniforms consumed)."""
+    out = np.empty(max(n, 1), dtype=np.float64)
+    used = lib().orc_ratio(seed & M64, offset & M64, n, mu, sigma, _p(out))
+    return out[:n], int(used)
+
+
+def ratio_accept(u: float, v: float) -> bool:
+    return bool(lib().orc_ratio_accept(u, v))
+
+
+def ratio_words(words, mu: float = 0.0, sigma: float = 1.0):
+    """Algorithm R on explicit hash words (u-word, v-word per candidate).
+    Returns (compacted values, mask words, number accepted)."""
+    w = np.ascontiguousarray(words, dtype=np.uint64)
+    ncand = w.size // 2
+    out = np.empty(max(ncand, 1), dtype=np.float64)
+    masks = np.empty(max((ncand + 63) // 64, 1), dtype=np.uint64)
+    a = int(lib().orc_ratio_words(_p(w), ncand, mu, sigma, _p(out), _p(masks)))
+    return out[:a], masks[:(ncand + 63) // 64], a
+
+
+def ratio_count(seed: int, offset: int, ncand: int) -> int:
+    return int(lib().orc_ratio_count(seed & M64, offset & M64, ncand))
+
+
+def ratio_trace(seed: int, offset: int, ncand: int):
+    nw = (ncand + 63) // 64
+    masks = np.empty(max(nw, 1), dtype=np.uint64)
+    pref = np.empty(max(nw, 1), dtype=np.uint64)
+    a = int(lib().orc_ratio_trace(seed & M64, offset & M64, ncand, _p(masks), _p(pref)))
+    return masks[:nw], pref[:nw], a
+
+
+def ratio_window(seed: int, offset: int, j0: int, ncand: int, mu: float = 0.0, sigma: float = 1.0):
+    out = np.empty(max(ncand, 1), dtype=np.float64)
+    a = int(lib().orc_ratio_window(seed & M64, offset & M64, j0, ncand, mu, sigma, _p(out)))
+    return out[:a]
 
 
 # ---------------------------------------------------------------- statistics

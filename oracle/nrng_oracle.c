@@ -1,8 +1,9 @@
 /*
  * nrng_oracle.c -- plain, slow, single-threaded FP64 reference for the
  * normal-deviate path: Box-Muller Algorithm B1 and the Polar method,
- * Algorithm P (Section 2), method B3 (Section 3) and method P2 (Section 4,
- * the Polar method with the radius factor of method B3) of Brent, "Fast Normal Random
+ * Algorithm P (Section 2), method B3 (Section 3), method P2 (Section 4,
+ * the Polar method with the radius factor of method B3) and Algorithm R
+ * (Section 5, the ratio method in its basic form) of Brent, "Fast Normal Random
  * Number Generators for Vector Processors", 1993.
  *
  * TEST INFRASTRUCTURE ONLY.  Nothing in the product library may include,
@@ -525,6 +526,132 @@ uint64_t orc_b3(uint64_t seed, uint64_t offset, uint64_t n, double mu, double si
             out[2 * k + 1] = y;
     }
     return 3 * npairs;
+}
+
+/* ------------------------------------------------------------------------
+ * Algorithm R, Section 5 (the ratio method of Kinderman and Monahan in its
+ * basic form): candidate j takes the uniforms u = u_{2j}, v = u_{2j+1};
+ *   x = sqrt(8/e) (v - 1/2) / (1 - u);
+ *   reject if x^2 > -4 ln(1 - u), else return sigma x + mu.
+ * The test is the ratio method's: (1 - u, sqrt(8/e)(v - 1/2)) must lie in
+ * the region u' <= exp(-x^2/4) whose area, over the rectangle's, is
+ * sqrt(pi e)/4, which gives the 8/sqrt(pi e) = 2.74 uniforms per normal
+ * the section states.  (Read literally, the inequality as printed would
+ * accept 76% of candidates and return a non-normal variable.)
+ * One value per accepted candidate, in increasing j; a stream of n values
+ * consumes 2 (j_last + 1) uniforms.  The test is taken in double precision,
+ * the precision of the paper's implementations.
+ * --------------------------------------------------------------------- */
+static double ratio_c(void)
+{
+    return sqrt(8.0 / M_E);
+}
+
+static int ratio_candidate(double c, double u, double v, double *x)
+{
+    double xv = c * (v - 0.5) / (1.0 - u);
+    *x = xv;
+    return !(xv * xv > -4.0 * log(1.0 - u));
+}
+
+int orc_ratio_accept(double u, double v)
+{
+    double x;
+    return ratio_candidate(ratio_c(), u, v, &x);
+}
+
+/* Algorithm R on explicit 64-bit hash words: candidate j is (w[2j], w[2j+1])
+ * read as u = (w >> 11) 2^-53, v likewise.  Accepted values are written
+ * compactly in order; mask_words as for orc_polar_xy.  Returns the number
+ * accepted. */
+uint64_t orc_ratio_words(const uint64_t *w, uint64_t ncand, double mu, double sigma, double *out,
+                         uint64_t *mask_words)
+{
+    double c = ratio_c();
+    uint64_t a = 0;
+    if (mask_words)
+        for (uint64_t i = 0; i < (ncand + 63) / 64; ++i)
+            mask_words[i] = 0;
+    for (uint64_t j = 0; j < ncand; ++j) {
+        double u = (double)(w[2 * j] >> 11) * 0x1p-53;
+        double v = (double)(w[2 * j + 1] >> 11) * 0x1p-53;
+        double x;
+        if (!ratio_candidate(c, u, v, &x))
+            continue;
+        if (mask_words)
+            mask_words[j / 64] |= 1ull << (j % 64);
+        if (out)
+            out[a] = sigma * x + mu;
+        ++a;
+    }
+    return a;
+}
+
+/* Algorithm R over the counter stream: n values; returns 2 (j_last + 1). */
+uint64_t orc_ratio(uint64_t seed, uint64_t offset, uint64_t n, double mu, double sigma, double *out)
+{
+    double c = ratio_c();
+    uint64_t written = 0, j = 0;
+    while (written < n) {
+        double u = orc_uniform(seed, offset + 2 * j);
+        double v = orc_uniform(seed, offset + 2 * j + 1);
+        double x;
+        if (ratio_candidate(c, u, v, &x))
+            out[written++] = sigma * x + mu;
+        ++j;
+    }
+    return 2 * j;
+}
+
+uint64_t orc_ratio_count(uint64_t seed, uint64_t offset, uint64_t ncand)
+{
+    double c = ratio_c();
+    uint64_t a = 0;
+    for (uint64_t j = 0; j < ncand; ++j) {
+        double x;
+        a += (uint64_t)ratio_candidate(c, orc_uniform(seed, offset + 2 * j), orc_uniform(seed, offset + 2 * j + 1),
+                                       &x);
+    }
+    return a;
+}
+
+/* Accept masks and per-word exclusive prefixes of candidates [0, ncand), as
+ * orc_polar_trace. */
+uint64_t orc_ratio_trace(uint64_t seed, uint64_t offset, uint64_t ncand, uint64_t *mask_words,
+                         uint64_t *word_prefix)
+{
+    double c = ratio_c();
+    uint64_t a = 0;
+    for (uint64_t wd = 0; wd < (ncand + 63) / 64; ++wd) {
+        uint64_t m = 0;
+        if (word_prefix)
+            word_prefix[wd] = a;
+        for (uint64_t b = 0; b < 64 && 64 * wd + b < ncand; ++b) {
+            uint64_t j = 64 * wd + b;
+            double x;
+            if (ratio_candidate(c, orc_uniform(seed, offset + 2 * j), orc_uniform(seed, offset + 2 * j + 1), &x)) {
+                m |= 1ull << b;
+                ++a;
+            }
+        }
+        mask_words[wd] = m;
+    }
+    return a;
+}
+
+/* Values of the accepted candidates in the window [j0, j0 + ncand), as
+ * orc_polar_window (one value per candidate). */
+uint64_t orc_ratio_window(uint64_t seed, uint64_t offset, uint64_t j0, uint64_t ncand, double mu, double sigma,
+                          double *out)
+{
+    double c = ratio_c();
+    uint64_t a = 0;
+    for (uint64_t j = j0; j < j0 + ncand; ++j) {
+        double x;
+        if (ratio_candidate(c, orc_uniform(seed, offset + 2 * j), orc_uniform(seed, offset + 2 * j + 1), &x))
+            out[a++] = sigma * x + mu;
+    }
+    return a;
 }
 
 /* ------------------------------------------------------------------------

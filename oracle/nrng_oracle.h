@@ -47,6 +47,16 @@ void orc_b3_u(const double *u1, const double *u2, const double *u3, uint64_t npa
 void orc_b3_words(const uint64_t *w, uint64_t npairs, double mu, double sigma, double *out);
 uint64_t orc_b3(uint64_t seed, uint64_t offset, uint64_t n, double mu, double sigma, double *out);
 
+int orc_ratio_accept(double u, double v);
+uint64_t orc_ratio_words(const uint64_t *w, uint64_t ncand, double mu, double sigma, double *out,
+                         uint64_t *mask_words);
+uint64_t orc_ratio(uint64_t seed, uint64_t offset, uint64_t n, double mu, double sigma, double *out);
+uint64_t orc_ratio_count(uint64_t seed, uint64_t offset, uint64_t ncand);
+uint64_t orc_ratio_trace(uint64_t seed, uint64_t offset, uint64_t ncand, uint64_t *mask_words,
+                         uint64_t *word_prefix);
+uint64_t orc_ratio_window(uint64_t seed, uint64_t offset, uint64_t j0, uint64_t ncand, double mu, double sigma,
+                          double *out);
+
 void orc_moments(const double *x, uint64_t n, double *out);
 double orc_normal_cdf(double z);
 double orc_ks(double *x, uint64_t n, int kind, double mu, double sigma);

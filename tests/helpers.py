@@ -9,7 +9,7 @@ import numpy as np
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
-_MATH_NS = {k: getattr(math, k) for k in ("sqrt", "log", "log1p", "pi", "sin", "cos")}
+_MATH_NS = {k: getattr(math, k) for k in ("sqrt", "log", "log1p", "pi", "sin", "cos", "exp")}
 
 
 def golden_rows(name: str):

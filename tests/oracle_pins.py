@@ -28,7 +28,11 @@ What pins what:
   * method B3 (Section 3): closed-form values (max rather than min, the
     order cos then sin, the shift by -pi, both sides of 8/9), the whole
     stream pair by pair against sqrt(-2 log1p(-m^2)) (cos t, sin t)
-    computed here, 3 uniforms per pair, and the distribution.
+    computed here, 3 uniforms per pair, and the distribution;
+  * Algorithm R (Section 5): closed-form accept/reject cases on both sides
+    of the curve x^2 = -4 ln(1 - u), the acceptance rate sqrt(pi e)/4 (the
+    2.74 uniforms per normal the section states), the stream's composition,
+    and the distribution of the accepted x.
 """
 from __future__ import annotations
 
@@ -447,6 +451,77 @@ def check_b3_distribution(n: int = 1 << 20):
     assert stats.kstest(e, "expon").statistic < 1.95 / math.sqrt(e.size)
 
 
+# ------------------------------------------------------------------ Algorithm R
+def _word(u: float) -> int:
+    return int(round(u * 2.0**53)) << 11
+
+
+def check_ratio_hand():
+    rows = golden_rows("ratio_hand_values.txt")
+    w = np.array([_word(closed_form(r[c])) for r in rows for c in range(2)], dtype=np.uint64)
+    out, masks, a = O.ratio_words(w)
+    acc = [int(r[2]) for r in rows]
+    assert a == sum(acc)
+    bits = [(int(masks[j // 64]) >> (j % 64)) & 1 for j in range(len(rows))]
+    assert bits == acc, (bits, acc)
+    k = 0
+    for r in rows:
+        assert O.ratio_accept(closed_form(r[0]), closed_form(r[1])) == (r[2] == "1")
+        if r[2] == "0":
+            continue
+        want, got = closed_form(r[3]), out[k]
+        kind, amt = r[4].split(":")
+        if kind == "abs" or want == 0.0:
+            assert abs(got - want) <= float(amt), (r, got, want)
+        else:
+            assert ulp_dist64([got], [want])[0] <= int(amt), (r, got, want)
+        k += 1
+    out2, _, _ = O.ratio_words(w, mu=2.0, sigma=3.0)
+    assert np.allclose(out2, 2.0 + 3.0 * out, rtol=0, atol=1e-13)
+
+
+def check_ratio_rate(ncand: int = 1 << 21):
+    a = O.ratio_count(0x5A7, 0, ncand)
+    p = math.sqrt(math.pi * math.e) / 4
+    assert abs(a / ncand - p) < 5 * math.sqrt(p * (1 - p) / ncand), a / ncand
+
+
+def check_ratio_stream():
+    seed, off, n = 0xA11, 9, 20001
+    z, used = O.ratio(seed, off, n)
+    ncand = used // 2
+    w = O.hashes(seed, off, used)
+    ref, masks, a = O.ratio_words(w)
+    assert a == n and np.array_equal(z, ref)
+    # the last candidate consumed supplied the last value
+    assert (int(masks[(ncand - 1) // 64]) >> ((ncand - 1) % 64)) & 1 == 1
+    tm, tp, ta = O.ratio_trace(seed, off, ncand)
+    assert np.array_equal(tm, masks) and ta == a
+    pc = np.concatenate([[0], np.cumsum([bin(int(m)).count("1") for m in masks])])[:-1]
+    assert np.array_equal(tp.astype(np.int64), pc)
+    assert O.ratio_count(seed, off, ncand) == a
+    j0 = 1000
+    win = O.ratio_window(seed, off, j0, 3000)
+    before = O.ratio_count(seed, off, j0)
+    assert np.array_equal(win, ref[before: before + win.size])
+    z1, u1 = O.ratio(seed, off, 1000)
+    z2, u2 = O.ratio(seed, off + u1, n - 1000)
+    assert np.array_equal(np.concatenate([z1, z2]), z) and u1 + u2 == used
+    zs, _ = O.ratio(seed, off, n, mu=-1.0, sigma=2.0)
+    assert np.allclose(zs, -1.0 + 2.0 * z, rtol=0, atol=1e-13)
+    # each accepted value against the formula written out here
+    u = (w[0::2] >> np.uint64(11)).astype(np.float64) * 2.0**-53
+    v = (w[1::2] >> np.uint64(11)).astype(np.float64) * 2.0**-53
+    x = math.sqrt(8 / math.e) * (v - 0.5) / (1 - u)
+    keep = x * x <= -4 * np.log1p(-u)
+    assert np.allclose(z, x[keep], rtol=1e-14, atol=1e-15)
+
+
+def check_ratio_distribution(n: int = 1 << 20):
+    z, _ = O.ratio(21, 0, n)
+    _dist_checks(z)
+
+
 def check_stats_routines():
     from scipy import special, stats
     g = np.random.Generator(np.random.PCG64(5))
@@ -476,5 +551,6 @@ ALL_CHECKS = [
     check_b1_composition, check_polar_hand, check_polar_lattice, check_polar_composition,
     check_polar_accept_rate, check_polar_s_uniform, check_b1_distribution, check_polar_distribution,
     check_stats_routines, check_p2_poly_bound, check_polar2_hand, check_polar2_lattice, check_polar2_vs_polar,
-    check_polar2_distribution, check_b3_hand, check_b3_stream, check_b3_distribution,
+    check_polar2_distribution, check_b3_hand, check_b3_stream, check_b3_distribution, check_ratio_hand,
+    check_ratio_rate, check_ratio_stream, check_ratio_distribution,
 ]

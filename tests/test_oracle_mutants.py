@@ -79,6 +79,17 @@ MUTANTS = {
     "b3_consumed": ("return 3 * npairs;", "return 2 * npairs;"),
     "b3_pairing": ("double u3 = orc_uniform(seed, offset + 3 * k + 2);", "double u3 = orc_uniform(seed, offset + 3 * k + 1);"),
     "b3_words_shift": ("double u3 = (double)(w[3 * p + 2] >> 11) * 0x1p-53;", "double u3 = (double)(w[3 * p + 2] >> 12) * 0x1p-52;"),
+    "r_const": ("return sqrt(8.0 / M_E);", "return sqrt(2.0 / M_E);"),
+    "r_center": ("double xv = c * (v - 0.5) / (1.0 - u);", "double xv = c * v / (1.0 - u);"),
+    "r_u_not_1mu": ("double xv = c * (v - 0.5) / (1.0 - u);", "double xv = c * (v - 0.5) / (u + 0x1p-60);"),
+    "r_four": ("return !(xv * xv > -4.0 * log(1.0 - u));", "return !(xv * xv > -2.0 * log(1.0 - u));"),
+    "r_direction": ("return !(xv * xv > -4.0 * log(1.0 - u));", "return xv * xv > -4.0 * log(1.0 - u);"),
+    "r_printed_form": ("return !(xv * xv > -4.0 * log(1.0 - u));", "return !(-(xv * xv) * log(1.0 - u) > 4.0);"),
+    "r_pairing": ("        double u = orc_uniform(seed, offset + 2 * j);\n        double v = orc_uniform(seed, offset + 2 * j + 1);\n        double x;\n        if (ratio_candidate(c, u, v, &x))\n            out[written++]",
+                  "        double v = orc_uniform(seed, offset + 2 * j);\n        double u = orc_uniform(seed, offset + 2 * j + 1);\n        double x;\n        if (ratio_candidate(c, u, v, &x))\n            out[written++]"),
+    "r_consumed": ("            out[written++] = sigma * x + mu;\n        ++j;\n    }\n    return 2 * j;", "            out[written++] = sigma * x + mu;\n        ++j;\n    }\n    return 2 * j + 2;"),
+    "r_sigma": ("            out[written++] = sigma * x + mu;", "            out[written++] = x + mu;"),
+    "r_trace_prefix": ("            word_prefix[wd] = a;", "            word_prefix[wd] = a + 1;"),
     "kurtosis": ("out[3] = m4 / (m2 * m2);", "out[3] = m4 / m2;"),
     "skew": ("out[2] = m3 / (m2 * sqrt(m2));", "out[2] = m3 / m2;"),
     "ks_step": ("double hi = (double)(i + 1) / (double)n - f;", "double hi = (double)i / (double)n - f;"),
