@@ -13,8 +13,8 @@ Alongside, outside the timed region: the measured store-only and hash-only
 ceilings, the single-stream fills of 2^30 normals (FP32, BF16, FP16 and the
 plain FP64 kernels, the comparison point of the FP32 batched figure), the
 graph-replayed repeated fill (64 x 2^28 Polar normals), methods P2 (Section
-4) and B3 (Section 3) on the same batched workload, and the CPU oracle timed
-on the host cores.
+4), B3 (Section 3) and Algorithm R (Section 5) on the same batched workload,
+and the CPU oracle timed on the host cores.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extras]
                        [--no-cpu] [--only b1|polar]
@@ -275,6 +275,8 @@ def main() -> int:
                                                            per_kernel, nb.NRNG_METHOD_P2)
         result["extras"]["b3_batched"] = extra_batched(nb, torch, stream, D, ns, total, pairs, args.steps,
                                                        per_kernel, nb.NRNG_METHOD_B3)
+        result["extras"]["ratio_batched"] = extra_batched(nb, torch, stream, D, ns, total, pairs, args.steps,
+                                                          per_kernel, nb.NRNG_METHOD_R)
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(cfg, [m for m, _ in methods])
     print(json.dumps(result), flush=True)
@@ -282,10 +284,11 @@ def main() -> int:
 
 
 def extra_batched(nb, torch, stream, D, ns, total, pairs, steps, per_kernel, m):
-    """Method P2 (Section 4) or B3 (Section 3) on the same batched workload,
-    timed like the step's legs: plan, then exec part 1 (P2: the mask and
-    scan kernels; B3: nothing) and part 2 (the generate kernel; the B3
-    kernel) between events."""
+    """Method P2 (Section 4), B3 (Section 3) or Algorithm R (Section 5) on the
+    same batched workload, timed like the step's legs: plan, then exec part 1
+    (P2, R: the mask and scan kernels; B3: nothing) and part 2 (the generate
+    kernel; the B3 kernel) between events.  R's mask kernel decides its test
+    in FP64, so no FP32 VALU fraction is given for it."""
     out = torch.empty(total, dtype=torch.float32, device=D["n"].device)
     cons = torch.zeros(ns, dtype=torch.int64, device=D["n"].device)
 
@@ -320,13 +323,17 @@ def extra_batched(nb, torch, stream, D, ns, total, pairs, steps, per_kernel, m):
         r.update({"count_ms": round(count_ms, 5), "generate_ms": round(gen_ms, 5), "candidates": cand})
         units = {"p2_count": (count_ms, ALU_OPS["p2_count"] * cand),
                  "p2_generate": (gen_ms, ALU_OPS["p2_generate"] * pairs)}
+    elif m == nb.NRNG_METHOD_R:
+        r.update({"count_ms": round(count_ms, 5), "generate_ms": round(gen_ms, 5),
+                  "candidates": int(u64sum(cons)) // 2})
+        units = {}
     else:
         r["consumed_uniforms"] = int(u64sum(cons))
         units = {"b3_batched": (gen_ms, ALU_OPS["b3_batched"] * pairs)}
     for k, (ms, ops) in units.items():
         r["alu"][k] = {"ms": round(ms, 5), "Tops_per_s": round(ops / (ms * 1e-3) / 1e12, 2),
                        "frac_valu_peak": round(ops / (ms * 1e-3) / 1e12 / VALU_PEAK_TOPS, 4)}
-    ref = "polar" if m == nb.NRNG_METHOD_P2 else "b1"
+    ref = "b1" if m == nb.NRNG_METHOD_B3 else "polar"
     if ref in per_kernel:
         r["exec_vs_" + ref] = round(per_kernel[ref]["exec_ms"] / exec_ms, 4)
     return r
@@ -378,6 +385,8 @@ def extras(nb, torch, dev, stream, per_kernel, batched_value):
         r["p2_normals_per_s"] = n / (ms * 1e-3)
         ms = timed(lambda: nb.nrng_b3(1, 0, n, 0.0, 1.0, out, dt, stream), 5)
         r["b3_normals_per_s"] = n / (ms * 1e-3)
+        ms = timed(lambda: nb.nrng_ratio(21, 0, n, 0.0, 1.0, out, dt, stream, None), 3)
+        r["ratio_normals_per_s"] = n / (ms * 1e-3)
         single[name] = r
         del out
         torch.cuda.empty_cache()

@@ -5,8 +5,8 @@
  * The library turns a counter-based stream of uniform deviates into
  * N(mu, sigma^2) deviates by the two methods of Section 2 of R. P. Brent,
  * "Fast Normal Random Number Generators for Vector Processors" (1993), and
- * by the paper's methods B3 (Section 3, see nrng_b3) and P2 (Section 4, see
- * nrng_polar2):
+ * by the paper's methods B3 (Section 3, see nrng_b3), P2 (Section 4, see
+ * nrng_polar2) and Algorithm R (Section 5, see nrng_ratio):
  *
  *   Algorithm B1 (Box-Muller):  r = sigma sqrt(-2 ln(1 - u)),
  *                               x = r sin(2 pi v) + mu,  y = r cos(2 pi v) + mu;
@@ -69,7 +69,13 @@ extern "C" {
 enum nrng_dtype { NRNG_F64 = 0, NRNG_F32 = 1, NRNG_BF16 = 2, NRNG_F16 = 3 };
 
 /* Methods for nrng_batched. */
-enum nrng_method { NRNG_METHOD_B1 = 0, NRNG_METHOD_POLAR = 1, NRNG_METHOD_P2 = 2, NRNG_METHOD_B3 = 3 };
+enum nrng_method {
+    NRNG_METHOD_B1 = 0,
+    NRNG_METHOD_POLAR = 1,
+    NRNG_METHOD_P2 = 2,
+    NRNG_METHOD_B3 = 3,
+    NRNG_METHOD_R = 4
+};
 
 /* Status codes. */
 enum nrng_status {
@@ -172,6 +178,24 @@ int nrng_polar2(uint64_t seed, uint64_t offset, uint64_t n, double mu, double si
  * same three kernels as nrng_polar and allocates nothing once the workspace
  * is reserved (nrng_reserve(n, 0)); NRNG_ECAPTURE otherwise while
  * capturing. */
+/* ------------------------------------------------------------------------
+ * Algorithm R (Section 5), the ratio method of Kinderman and Monahan in its
+ * basic form, over one stream.  Candidate j uses the uniforms u = u_{2j} and
+ * v = u_{2j+1} (same uniform definition as B1):
+ *   x = sqrt(8/e) (v - 1/2) / (1 - u); accepted iff x^2 <= -4 ln(1 - u);
+ *   the a-th accepted candidate writes output a = sigma x + mu.
+ * (The test is the ratio method's, which gives the 8/sqrt(pi e) = 2.74
+ * uniforms per normal that Section 5 states; the inequality as printed there
+ * would accept 76% of candidates and not give a normal variable.)  The test
+ * is decided in FP64, so accept masks, output indices and consumed counts
+ * are exact; values are computed in the output's precision class as for the
+ * other methods.  Runs as the Polar kernels (mask, scan, generate) with one
+ * output per accepted candidate.  consumed = 2 (j_last + 1).  Arguments,
+ * errors, workspace and launch configuration (nrng_tune_set kernel 1) as
+ * nrng_polar. */
+int nrng_ratio(uint64_t seed, uint64_t offset, uint64_t n, double mu, double sigma, void *out, int dtype,
+               void *stream, uint64_t *d_consumed);
+
 int nrng_polar_dev(uint64_t seed, uint64_t *d_cursor, uint64_t n, double mu, double sigma, void *out,
                    int dtype, void *stream);
 
@@ -179,7 +203,7 @@ int nrng_polar_dev(uint64_t seed, uint64_t *d_cursor, uint64_t n, double mu, dou
  * Many independent streams in one launch sequence: one small set-up kernel
  * builds the tile table on the device, then one persistent B1 kernel, or
  * the three Polar kernels, cover every stream.
- *   method       NRNG_METHOD_B1, NRNG_METHOD_POLAR, NRNG_METHOD_P2 or NRNG_METHOD_B3
+ *   method       NRNG_METHOD_B1, NRNG_METHOD_POLAR, NRNG_METHOD_P2, NRNG_METHOD_B3 or NRNG_METHOD_R
  *   nstreams     number of streams (0 is a no-op)
  *   d_seed[j], d_offset[j], d_n[j]  stream j's seed, first counter, length
  *   d_out_off[j] element offset of stream j's output in `out`; NULL means
@@ -189,7 +213,7 @@ int nrng_polar_dev(uint64_t seed, uint64_t *d_cursor, uint64_t n, double mu, dou
  *                range [out_off, out_off + n) does not fit are skipped
  *   d_consumed   optional (may be NULL): d_consumed[j] receives stream j's
  *                consumed uniforms, or UINT64_MAX if the stream was skipped.
- * Stream j's values equal those of nrng_boxmuller / nrng_polar / nrng_polar2 / nrng_b3 called alone
+ * Stream j's values equal those of nrng_boxmuller / nrng_polar / nrng_polar2 / nrng_b3 / nrng_ratio called alone
  * with (d_seed[j], d_offset[j], d_n[j], d_mu[j], d_sigma[j]), bit for bit.
  * The total of d_n over valid streams must not exceed out_len; otherwise the
  * device-side check fails the whole call (every d_consumed[j] = UINT64_MAX,
@@ -239,8 +263,9 @@ int nrng_fillgraph_launch(void *graph, void *stream);
 int nrng_fillgraph_destroy(void *graph);
 
 /* ------------------------------------------------------------------------
- * Launch configuration.  kernel: 0 = B1 and B3 single stream, 1 = Polar and
- * P2 (single, device cursor and batched), 2 = B1 and B3 batched.  Sets the workgroup size and
+ * Launch configuration.  kernel: 0 = B1 and B3 single stream, 1 = Polar, P2
+ * and Algorithm R (single, device cursor and batched), 2 = B1 and B3
+ * batched.  Sets the workgroup size and
  * per-thread unroll used for `dtype`; NRNG_EINVAL if that pair is not one of
  * the compiled variants (nrng_tune_variants lists them as (wg, unroll)
  * pairs).  grid_per_cu (0 = from the occupancy query) caps the persistent
@@ -262,6 +287,12 @@ int nrng_tune_variants(int kernel, uint32_t *pairs, int max_pairs);
  *   d_mask_words (ceil(ncand/64) words, bit j%64 of word j/64 = accept) and
  *   *d_count (number accepted) are written.
  * nrng_test_polar2_xy: the same for method P2 (accepts 0 <= S < 2^62).
+ * nrng_test_ratio_words: Algorithm R on explicit candidates, candidate j
+ *   being the 64-bit words (d_words[2j], d_words[2j+1]) read as u and v;
+ *   outputs, masks and count as nrng_test_polar_xy (one output per accepted
+ *   candidate).
+ * nrng_ratio_trace: Algorithm R's accept masks and word prefixes over
+ *   candidates [0, ncand) of stream (seed, offset), as nrng_polar_trace.
  * nrng_polar_trace: the accept masks and, per 64-candidate word, the output
  *   pair index of its first candidate (exclusive prefix), for candidates
  *   [0, ncand) of stream (seed, offset), produced by the production Polar
@@ -269,7 +300,7 @@ int nrng_tune_variants(int kernel, uint32_t *pairs, int max_pairs);
  * nrng_test_polar_budget: nrng_polar with the candidate budget forced to
  *   `words` (>= 1) words of 64 candidates, to exercise the exact
  *   continuation path that runs when a stream needs more candidates than its
- *   budget.
+ *   budget.  nrng_test_ratio_budget: the same for nrng_ratio.
  * ---------------------------------------------------------------------- */
 int nrng_test_b1_words(const uint64_t *d_words, uint64_t npairs, double mu, double sigma, void *out, int dtype,
                        void *stream);
@@ -279,9 +310,15 @@ int nrng_test_polar_xy(const int32_t *d_xy, uint64_t ncand, double mu, double si
                        uint64_t *d_mask_words, uint64_t *d_count, void *stream);
 int nrng_test_polar2_xy(const int32_t *d_xy, uint64_t ncand, double mu, double sigma, void *out, int dtype,
                         uint64_t *d_mask_words, uint64_t *d_count, void *stream);
+int nrng_test_ratio_words(const uint64_t *d_words, uint64_t ncand, double mu, double sigma, void *out, int dtype,
+                          uint64_t *d_mask_words, uint64_t *d_count, void *stream);
+int nrng_ratio_trace(uint64_t seed, uint64_t offset, uint64_t ncand, uint64_t *d_mask_words,
+                     uint64_t *d_word_prefix, void *stream);
 int nrng_polar_trace(uint64_t seed, uint64_t offset, uint64_t ncand, uint64_t *d_mask_words,
                      uint64_t *d_word_prefix, void *stream);
 int nrng_test_polar_budget(uint64_t seed, uint64_t offset, uint64_t n, double mu, double sigma, void *out,
+                           int dtype, uint32_t words, void *stream, uint64_t *d_consumed);
+int nrng_test_ratio_budget(uint64_t seed, uint64_t offset, uint64_t n, double mu, double sigma, void *out,
                            int dtype, uint32_t words, void *stream, uint64_t *d_consumed);
 
 /* ------------------------------------------------------------------------

@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libnrng.so")
 
 NRNG_F64, NRNG_F32, NRNG_BF16, NRNG_F16 = 0, 1, 2, 3
-NRNG_METHOD_B1, NRNG_METHOD_POLAR, NRNG_METHOD_P2, NRNG_METHOD_B3 = 0, 1, 2, 3
+NRNG_METHOD_B1, NRNG_METHOD_POLAR, NRNG_METHOD_P2, NRNG_METHOD_B3, NRNG_METHOD_R = 0, 1, 2, 3, 4
 NRNG_OK, NRNG_EINVAL, NRNG_EDTYPE, NRNG_ERANGE = 0, -1, -2, -3
 NRNG_EHIP, NRNG_ENODEV, NRNG_ECAPTURE, NRNG_ENOMEM = -4, -5, -6, -7
 KERNEL_B1, KERNEL_POLAR, KERNEL_B1_BATCHED = 0, 1, 2
@@ -35,6 +35,7 @@ _SIGS = {
     "nrng_b3": (_i32, [_u64, _u64, _u64, _f64, _f64, _vp, _i32, _vp]),
     "nrng_polar": (_i32, [_u64, _u64, _u64, _f64, _f64, _vp, _i32, _vp, _vp]),
     "nrng_polar2": (_i32, [_u64, _u64, _u64, _f64, _f64, _vp, _i32, _vp, _vp]),
+    "nrng_ratio": (_i32, [_u64, _u64, _u64, _f64, _f64, _vp, _i32, _vp, _vp]),
     "nrng_polar_dev": (_i32, [_u64, _vp, _u64, _f64, _f64, _vp, _i32, _vp]),
     "nrng_batched": (_i32, [_i32, _u32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _u64, _i32, _vp, _vp]),
     "nrng_batched_plan": (_i32, [_i32, _u32, _vp, _vp, _u64, _i32, _vp, _vp]),
@@ -50,8 +51,11 @@ _SIGS = {
     "nrng_test_b3_words": (_i32, [_vp, _u64, _f64, _f64, _vp, _i32, _vp]),
     "nrng_test_polar_xy": (_i32, [_vp, _u64, _f64, _f64, _vp, _i32, _vp, _vp, _vp]),
     "nrng_test_polar2_xy": (_i32, [_vp, _u64, _f64, _f64, _vp, _i32, _vp, _vp, _vp]),
+    "nrng_test_ratio_words": (_i32, [_vp, _u64, _f64, _f64, _vp, _i32, _vp, _vp, _vp]),
+    "nrng_ratio_trace": (_i32, [_u64, _u64, _u64, _vp, _vp, _vp]),
     "nrng_polar_trace": (_i32, [_u64, _u64, _u64, _vp, _vp, _vp]),
     "nrng_test_polar_budget": (_i32, [_u64, _u64, _u64, _f64, _f64, _vp, _i32, _u32, _vp, _vp]),
+    "nrng_test_ratio_budget": (_i32, [_u64, _u64, _u64, _f64, _f64, _vp, _i32, _u32, _vp, _vp]),
     "nrng_probe_store": (_i32, [_vp, _u64, _vp]),
     "nrng_probe_copy": (_i32, [_vp, _vp, _u64, _vp]),
     "nrng_probe_hash": (_i32, [_u64, _u64, _vp, _u64, _vp]),
@@ -171,6 +175,13 @@ def nrng_polar2(seed, offset, n, mu, sigma, out, dtype, stream=None, d_consumed=
                                             dtype, _stream(stream), _ptr(d_consumed)))
 
 
+def nrng_ratio(seed, offset, n, mu, sigma, out, dtype, stream=None, d_consumed=None) -> None:
+    _need(out, n * _ESIZE.get(dtype, 0), "nrng_ratio out")
+    _need(d_consumed, 8, "nrng_ratio d_consumed")
+    _check("nrng_ratio", lib().nrng_ratio(seed & (2**64 - 1), offset & (2**64 - 1), n, mu, sigma, _ptr(out), dtype,
+                                          _stream(stream), _ptr(d_consumed)))
+
+
 def nrng_polar_dev(seed, d_cursor, n, mu, sigma, out, dtype, stream=None) -> None:
     _need(out, n * _ESIZE.get(dtype, 0), "nrng_polar_dev out")
     _need(d_cursor, 8, "nrng_polar_dev d_cursor")
@@ -285,6 +296,22 @@ def nrng_test_polar2_xy(d_xy, ncand, mu, sigma, out, dtype, d_mask_words, d_coun
                                                             _ptr(d_mask_words), _ptr(d_count), _stream(stream)))
 
 
+def nrng_test_ratio_words(d_words, ncand, mu, sigma, out, dtype, d_mask_words, d_count, stream=None) -> None:
+    _need(d_words, 16 * ncand, "nrng_test_ratio_words d_words")
+    _need(out, ncand * _ESIZE.get(dtype, 0), "nrng_test_ratio_words out")
+    _need(d_mask_words, 8 * ((ncand + 63) // 64), "nrng_test_ratio_words d_mask_words")
+    _need(d_count, 8, "nrng_test_ratio_words d_count")
+    _check("nrng_test_ratio_words", lib().nrng_test_ratio_words(_ptr(d_words), ncand, mu, sigma, _ptr(out), dtype,
+                                                                _ptr(d_mask_words), _ptr(d_count), _stream(stream)))
+
+
+def nrng_ratio_trace(seed, offset, ncand, d_mask_words, d_word_prefix, stream=None) -> None:
+    _need(d_mask_words, 8 * ((ncand + 63) // 64), "nrng_ratio_trace d_mask_words")
+    _need(d_word_prefix, 8 * ((ncand + 63) // 64), "nrng_ratio_trace d_word_prefix")
+    _check("nrng_ratio_trace", lib().nrng_ratio_trace(seed & (2**64 - 1), offset & (2**64 - 1), ncand,
+                                                      _ptr(d_mask_words), _ptr(d_word_prefix), _stream(stream)))
+
+
 def nrng_polar_trace(seed, offset, ncand, d_mask_words, d_word_prefix, stream=None) -> None:
     _need(d_mask_words, 8 * ((ncand + 63) // 64), "nrng_polar_trace d_mask_words")
     _need(d_word_prefix, 8 * ((ncand + 63) // 64), "nrng_polar_trace d_word_prefix")
@@ -296,6 +323,14 @@ def nrng_test_polar_budget(seed, offset, n, mu, sigma, out, dtype, words, stream
     _need(out, n * _ESIZE.get(dtype, 0), "nrng_test_polar_budget out")
     _need(d_consumed, 8, "nrng_test_polar_budget d_consumed")
     _check("nrng_test_polar_budget", lib().nrng_test_polar_budget(seed & (2**64 - 1), offset & (2**64 - 1), n, mu,
+                                                                  sigma, _ptr(out), dtype, words, _stream(stream),
+                                                                  _ptr(d_consumed)))
+
+
+def nrng_test_ratio_budget(seed, offset, n, mu, sigma, out, dtype, words, stream=None, d_consumed=None) -> None:
+    _need(out, n * _ESIZE.get(dtype, 0), "nrng_test_ratio_budget out")
+    _need(d_consumed, 8, "nrng_test_ratio_budget d_consumed")
+    _check("nrng_test_ratio_budget", lib().nrng_test_ratio_budget(seed & (2**64 - 1), offset & (2**64 - 1), n, mu,
                                                                   sigma, _ptr(out), dtype, words, _stream(stream),
                                                                   _ptr(d_consumed)))
 

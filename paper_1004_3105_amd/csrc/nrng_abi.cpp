@@ -34,8 +34,8 @@ struct DevState {
     uint64_t *stream_words = nullptr;
     uint64_t *packed_off = nullptr;
     uint64_t stream_cap = 0;
-    int occ_polar[2][4][4][8] = {};  // generate kernel: [value method][mode][dtype][variant], 0 = not queried
-    int occ_mask[2][4][8] = {};      // mask kernel: [value method][mode][variant]
+    int occ_polar[3][4][4][8] = {};  // generate kernel: [value method][mode][dtype][variant], 0 = not queried
+    int occ_mask[3][4][8] = {};      // mask kernel: [value method][mode][variant]
     int occ_b1[2][2][4][8] = {};     // [B1 / B3][batched][dtype][variant]
     // the tile table currently in the workspace (from nrng_batched_plan)
     int plan_method = -1, plan_dtype = -1, plan_vi = -1;
@@ -230,12 +230,17 @@ uint64_t polar_gen_waves(int vi)
 }
 
 // Upper bound on the total candidate budget, in words, of a batch whose valid
-// streams hold at most out_len normals: each stream of P >= 1 pairs has a
-// budget of at most (3.6346 P + 64) / 64 + 1 words (see polar_budget_words).
-uint64_t batched_polar_word_bound(uint64_t out_len, uint64_t nstreams)
+// streams hold at most out_len normals.  A stream needing N >= 1 accepted
+// candidates at acceptance p has a budget of at most (F N + 64) / 64 + 1
+// words with F = (1 + 4 sqrt(1 - p)) / p (candidate_budget_words, with
+// sqrt(N) <= N): F = 3.6346 for Polar and P2 (N = ceil(n/2) pairs, p = pi/4)
+// and 4.2116 for Algorithm R (N = n, p = sqrt(pi e)/4).
+uint64_t batched_word_bound(int method, uint64_t out_len, uint64_t nstreams)
 {
-    const double pairs = ((double)out_len + (double)nstreams) / 2.0;
-    const double b = (3.6346 * pairs + 64.0 * (double)nstreams) / 64.0 + (double)nstreams + 2.0;
+    const bool ratio = method == NRNG_METHOD_R;
+    const double need = ratio ? (double)out_len : ((double)out_len + (double)nstreams) / 2.0;
+    const double F = ratio ? 4.2116 : 3.6346;
+    const double b = (F * need + 64.0 * (double)nstreams) / 64.0 + (double)nstreams + 2.0;
     if (b > 1.0e15)
         return ~0ull;
     return (uint64_t)b;
@@ -259,11 +264,14 @@ PolarArgs polar_args(DevState &d)
     a.csum = d.csum;
     a.cpfx = d.cpfx;
     a.misc = d.misc;
+    a.ratio_c = std::sqrt(8.0 / M_E);   // Algorithm R's sqrt(8/e): 8 / e rounded to double, then the root
     return a;
 }
 
-// Value method of a batched method id (Polar kernels only).
-int method_vm(int method) { return method == NRNG_METHOD_P2 ? 1 : 0; }
+// Value method of a method id (Polar kernels only): 0 = Algorithm P,
+// 1 = P2, 2 = Algorithm R.
+int method_vm(int method) { return method == NRNG_METHOD_P2 ? 1 : (method == NRNG_METHOD_R ? 2 : 0); }
+int vm_method(int vm) { return vm == 1 ? NRNG_METHOD_P2 : (vm == 2 ? NRNG_METHOD_R : NRNG_METHOD_POLAR); }
 
 // Box-Muller family (B1, B3): one kernel per tile of pairs, no compaction.
 bool method_bm(int method) { return method == NRNG_METHOD_B1 || method == NRNG_METHOD_B3; }
@@ -271,7 +279,7 @@ bool method_bm(int method) { return method == NRNG_METHOD_B1 || method == NRNG_M
 bool method_ok(int method)
 {
     return method == NRNG_METHOD_B1 || method == NRNG_METHOD_POLAR || method == NRNG_METHOD_P2 ||
-           method == NRNG_METHOD_B3;
+           method == NRNG_METHOD_B3 || method == NRNG_METHOD_R;
 }
 
 // B1 (bm 0) or B3 (bm 1) over one stream.
@@ -332,9 +340,9 @@ int bm_words(int bm, const uint64_t *d_words, uint64_t npairs, double mu, double
     return hip_status(launch_b1_words(bm, dtype, a, npairs, s));
 }
 
-// Single-stream Polar or P2 (also the device-cursor form): `words` is the
-// candidate budget, normally polar_budget_words of the pair count (P2
-// accepts at the same rate, pi/4 plus the measure-zero point s = 0).
+// Single-stream Polar, P2 or Algorithm R (also the device-cursor form):
+// `words` is the candidate budget, normally method_budget_words of n (P2
+// accepts at Polar's rate, pi/4 plus the measure-zero point s = 0).
 int polar_common(int vm, uint64_t seed, uint64_t offset, uint64_t *cursor, uint64_t n, double mu, double sigma,
                  void *out, int dtype, hipStream_t s, uint64_t *d_consumed, uint64_t force_words)
 {
@@ -355,7 +363,7 @@ int polar_common(int vm, uint64_t seed, uint64_t offset, uint64_t *cursor, uint6
         return rc;
     const Tune tu = g_tune[1][dtype];
     const uint64_t U = polar_tile_words(tu.vi);
-    const uint64_t words = force_words ? force_words : polar_budget_words((n + 1) / 2);
+    const uint64_t words = force_words ? force_words : method_budget_words(vm_method(vm), n);
     const uint64_t tiles = (words + U - 1) / U;
     if ((rc = ensure_polar_ws(*d, tiles, tiles * U, s)))
         return rc;
@@ -379,9 +387,9 @@ int polar_common(int vm, uint64_t seed, uint64_t offset, uint64_t *cursor, uint6
 }
 
 // Trace and explicit-candidate hooks: masks go to the caller's buffer.
-int polar_hook(int mode, int vm, uint64_t seed, uint64_t offset, uint64_t ncand, const int32_t *xy, double mu,
-               double sigma, void *out, int dtype, uint64_t *masks, uint64_t *word_prefix, uint64_t *count,
-               hipStream_t s)
+int polar_hook(int mode, int vm, uint64_t seed, uint64_t offset, uint64_t ncand, const int32_t *xy,
+               const uint64_t *uvw, double mu, double sigma, void *out, int dtype, uint64_t *masks,
+               uint64_t *word_prefix, uint64_t *count, hipStream_t s)
 {
     std::lock_guard<std::mutex> lk(g_mu);
     DevState *d;
@@ -406,6 +414,7 @@ int polar_hook(int mode, int vm, uint64_t seed, uint64_t offset, uint64_t ncand,
     a.masks = masks;
     a.word_prefix = word_prefix;
     a.xy = xy;
+    a.uvw = uvw;
     a.count_out = count;
     const uint64_t chunks = (tiles + kChunkTiles - 1) / kChunkTiles;
     const uint32_t gm = persistent_grid(*d, polar_mask_blocks_per_cu(*d, mode, vm, tu.vi), 0, chunks);
@@ -461,8 +470,11 @@ int nrng_reserve(uint64_t max_n, uint32_t max_streams)
         return rc;
     const Variant *v;
     const int nv = polar_variants(&v);
-    const uint64_t sw = polar_budget_words((max_n + 1) / 2);
-    const uint64_t wb = max_streams ? batched_polar_word_bound(max_n, max_streams) : 0;
+    // the larger of the Polar / P2 and the Algorithm R needs
+    const uint64_t sw = method_budget_words(NRNG_METHOD_R, max_n) > method_budget_words(NRNG_METHOD_POLAR, max_n)
+                            ? method_budget_words(NRNG_METHOD_R, max_n)
+                            : method_budget_words(NRNG_METHOD_POLAR, max_n);
+    const uint64_t wb = max_streams ? batched_word_bound(NRNG_METHOD_R, max_n, max_streams) : 0;
     if (wb == ~0ull)
         return NRNG_ERANGE;
     uint64_t tiles = 0, words = 0;
@@ -508,6 +520,12 @@ int nrng_polar2(uint64_t seed, uint64_t offset, uint64_t n, double mu, double si
     return polar_common(1, seed, offset, nullptr, n, mu, sigma, out, dtype, S(stream), d_consumed, 0);
 }
 
+int nrng_ratio(uint64_t seed, uint64_t offset, uint64_t n, double mu, double sigma, void *out, int dtype,
+               void *stream, uint64_t *d_consumed)
+{
+    return polar_common(2, seed, offset, nullptr, n, mu, sigma, out, dtype, S(stream), d_consumed, 0);
+}
+
 int nrng_polar_dev(uint64_t seed, uint64_t *d_cursor, uint64_t n, double mu, double sigma, void *out, int dtype,
                    void *stream)
 {
@@ -522,6 +540,14 @@ int nrng_test_polar_budget(uint64_t seed, uint64_t offset, uint64_t n, double mu
     if (words == 0)
         return NRNG_EINVAL;
     return polar_common(0, seed, offset, nullptr, n, mu, sigma, out, dtype, S(stream), d_consumed, words);
+}
+
+int nrng_test_ratio_budget(uint64_t seed, uint64_t offset, uint64_t n, double mu, double sigma, void *out,
+                           int dtype, uint32_t words, void *stream, uint64_t *d_consumed)
+{
+    if (words == 0)
+        return NRNG_EINVAL;
+    return polar_common(2, seed, offset, nullptr, n, mu, sigma, out, dtype, S(stream), d_consumed, words);
 }
 
 int nrng_batched_plan(int method, uint32_t nstreams, const uint64_t *d_n, const uint64_t *d_out_off,
@@ -564,7 +590,7 @@ int nrng_batched_plan(int method, uint32_t nstreams, const uint64_t *d_n, const 
         p.unit = (uint64_t)v[tu.vi].wg * v[tu.vi].unroll * ppl;
     } else {
         const uint64_t U = polar_tile_words(tu.vi);
-        const uint64_t wb = batched_polar_word_bound(out_len, nstreams);
+        const uint64_t wb = batched_word_bound(method, out_len, nstreams);
         if (wb == ~0ull)
             return NRNG_ERANGE;
         uint64_t tiles, words;
@@ -827,8 +853,8 @@ int nrng_test_polar_xy(const int32_t *d_xy, uint64_t ncand, double mu, double si
         return NRNG_OK;
     if (!d_xy || !out || !d_mask_words || !d_count)
         return NRNG_EINVAL;
-    return polar_hook(MODE_XY, 0, 0, 0, ncand, d_xy, mu, sigma, out, dtype, d_mask_words, nullptr, d_count,
-                      S(stream));
+    return polar_hook(MODE_XY, 0, 0, 0, ncand, d_xy, nullptr, mu, sigma, out, dtype, d_mask_words, nullptr,
+                      d_count, S(stream));
 }
 
 int nrng_test_polar2_xy(const int32_t *d_xy, uint64_t ncand, double mu, double sigma, void *out, int dtype,
@@ -843,8 +869,35 @@ int nrng_test_polar2_xy(const int32_t *d_xy, uint64_t ncand, double mu, double s
         return NRNG_OK;
     if (!d_xy || !out || !d_mask_words || !d_count)
         return NRNG_EINVAL;
-    return polar_hook(MODE_XY, 1, 0, 0, ncand, d_xy, mu, sigma, out, dtype, d_mask_words, nullptr, d_count,
-                      S(stream));
+    return polar_hook(MODE_XY, 1, 0, 0, ncand, d_xy, nullptr, mu, sigma, out, dtype, d_mask_words, nullptr,
+                      d_count, S(stream));
+}
+
+int nrng_test_ratio_words(const uint64_t *d_words, uint64_t ncand, double mu, double sigma, void *out, int dtype,
+                          uint64_t *d_mask_words, uint64_t *d_count, void *stream)
+{
+    if (!dtype_ok(dtype))
+        return NRNG_EDTYPE;
+    int rc = check_mu_sigma(mu, sigma);
+    if (rc)
+        return rc;
+    if (ncand == 0)
+        return NRNG_OK;
+    if (!d_words || !out || !d_mask_words || !d_count)
+        return NRNG_EINVAL;
+    return polar_hook(MODE_XY, 2, 0, 0, ncand, nullptr, d_words, mu, sigma, out, dtype, d_mask_words, nullptr,
+                      d_count, S(stream));
+}
+
+int nrng_ratio_trace(uint64_t seed, uint64_t offset, uint64_t ncand, uint64_t *d_mask_words,
+                     uint64_t *d_word_prefix, void *stream)
+{
+    if (ncand == 0)
+        return NRNG_OK;
+    if (!d_mask_words || !d_word_prefix)
+        return NRNG_EINVAL;
+    return polar_hook(MODE_TRACE, 2, seed, offset, ncand, nullptr, nullptr, 0.0, 1.0, nullptr, NRNG_F32,
+                      d_mask_words, d_word_prefix, nullptr, S(stream));
 }
 
 int nrng_polar_trace(uint64_t seed, uint64_t offset, uint64_t ncand, uint64_t *d_mask_words,
@@ -854,8 +907,8 @@ int nrng_polar_trace(uint64_t seed, uint64_t offset, uint64_t ncand, uint64_t *d
         return NRNG_OK;
     if (!d_mask_words || !d_word_prefix)
         return NRNG_EINVAL;
-    return polar_hook(MODE_TRACE, 0, seed, offset, ncand, nullptr, 0.0, 1.0, nullptr, NRNG_F32, d_mask_words,
-                      d_word_prefix, nullptr, S(stream));
+    return polar_hook(MODE_TRACE, 0, seed, offset, ncand, nullptr, nullptr, 0.0, 1.0, nullptr, NRNG_F32,
+                      d_mask_words, d_word_prefix, nullptr, S(stream));
 }
 
 int nrng_probe_store(void *out, uint64_t nbytes, void *stream)

@@ -1,9 +1,9 @@
 // nrng_device.hpp -- device-side building blocks of the normal-deviate
 // kernels for gfx950: the counter-based uniform source, the per-pair
 // transforms of Box-Muller (Algorithm B1) and the Polar method (Algorithm P)
-// [Brent 1993, Section 2] and of methods B3 (Section 3) and P2 (Section 4),
-// output conversion and store helpers, and the wavefront primitives of the
-// Polar compaction.
+// [Brent 1993, Section 2], of methods B3 (Section 3) and P2 (Section 4) and
+// of Algorithm R (Section 5), output conversion and store helpers, and the
+// wavefront primitives of the Polar compaction.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -43,6 +43,14 @@ __device__ __forceinline__ uint32_t splitmix64_mix_hi(uint64_t z)
 }
 
 __device__ __forceinline__ uint32_t splitmix64_hi(uint64_t c) { return splitmix64_mix_hi(c + kGamma); }
+
+// The full hash of counter c, given z = c + kGamma.
+__device__ __forceinline__ uint64_t splitmix64_mix(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
 
 // ---------------------------------------------------------------------------
 // Output element types.  OutT is the storage type; the arithmetic is FP64 for
@@ -136,6 +144,14 @@ __device__ __forceinline__ float cvt_f32_u32(uint32_t x)
 {
     float r;
     asm("v_cvt_f32_u32 %0, %1" : "=v"(r) : "v"(x));
+    return r;
+}
+
+// One v_cvt_f32_i32, for the same reason.
+__device__ __forceinline__ float cvt_f32_i32(int32_t x)
+{
+    float r;
+    asm("v_cvt_f32_i32 %0, %1" : "=v"(r) : "v"(x));
     return r;
 }
 
@@ -492,6 +508,50 @@ __device__ __forceinline__ float polar2_r31_f32(uint64_t S, float ks31, float k2
     const float sf = hf * 0x1p-30f;
     const float rl = __builtin_amdgcn_sqrtf(__builtin_amdgcn_logf(tf) * k2 * __builtin_amdgcn_rcpf(sf));
     return select_lanes(__ballot(polar2_big(S)), h * ks31, rl * 0x1p-31f);
+}
+
+// ---------------------------------------------------------------------------
+// Algorithm R (Section 5; the ratio method in its basic form).  Candidate j
+// takes the uniforms u = (k_u >> 11) 2^-53 and v = (k_v >> 11) 2^-53 of
+// counters 2j and 2j + 1; x = c (v - 1/2)/(1 - u) with c = sqrt(8/e); the
+// candidate is accepted iff x^2 <= -4 ln(1 - u) and then yields sigma x + mu.
+// The test is decided in FP64 (the paper's precision), in the oracle's order
+// of operations; c is sqrt(8.0 / e) rounded as the host computes it.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool ratio_accept(uint64_t ku, uint64_t kv, double c)
+{
+#pragma clang fp contract(off)
+    const double u = (double)(ku >> 11) * 0x1p-53;
+    const double v = (double)(kv >> 11) * 0x1p-53;
+    const double x = c * (v - 0.5) / (1.0 - u);
+    return !(x * x > -4.0 * log(1.0 - u));
+}
+
+__device__ __forceinline__ double ratio_value_f64(uint64_t ku, uint64_t kv, double c, double mu, double sigma)
+{
+#pragma clang fp contract(off)
+    const double u = (double)(ku >> 11) * 0x1p-53;
+    const double v = (double)(kv >> 11) * 0x1p-53;
+    const double x = c * (v - 0.5) / (1.0 - u);
+    return sigma * x + mu;
+}
+
+// FP32 value: x = c (v - 1/2)/(1 - u) = c dv / du with the 53-bit integers
+// dv = (k_v >> 11) - 2^52 and du = 2^53 - (k_u >> 11) >= 1 (the scale 2^-53
+// cancels), each converted with relative error below 2^-23; one reciprocal.
+// The signed dv is split at bit 21: the low part (below 2^21) converts
+// exactly and the high part exactly while |dv| < 2^45, so a small negative dv
+// (v just below 1/2, which matters when 1 - u is tiny) is not lost to a
+// rounded low word cancelling against the high one.
+__device__ __forceinline__ float ratio_value_f32(uint64_t ku, uint64_t kv, float c, float mu, float sigma)
+{
+    const int64_t dv = (int64_t)(kv >> 11) - (1ll << 52);
+    const uint64_t du = (1ull << 53) - (ku >> 11);
+    const float fv = __builtin_fmaf(cvt_f32_i32((int32_t)(dv >> 21)), 0x1p21f,
+                                    cvt_f32_u32((uint32_t)dv & 0x1FFFFFu));
+    const float fu = u64_to_f32_scaled(du, 0x1p32f, 1.0f);
+    const float x = c * fv * __builtin_amdgcn_rcpf(fu);
+    return __builtin_fmaf(sigma, x, mu);
 }
 
 // ---------------------------------------------------------------------------

@@ -53,8 +53,11 @@ struct PolarArgs {
     // trace / explicit candidates
     uint64_t ncand;
     uint64_t *word_prefix;
-    const int32_t *xy;
+    const int32_t *xy;       // Polar, P2: explicit (X, Y) pairs
+    const uint64_t *uvw;     // Algorithm R: explicit (u-word, v-word) pairs
     uint64_t *count_out;
+    // Algorithm R: sqrt(8/e), rounded as the host computes it
+    double ratio_c;
 };
 
 struct B1Args {
@@ -71,7 +74,7 @@ struct B1Args {
 };
 
 struct PrepArgs {
-    int method;                      // 0 = B1, 1 = Polar, 2 = P2, 3 = B3
+    int method;                      // 0 = B1, 1 = Polar, 2 = P2, 3 = B3, 4 = Algorithm R
     uint32_t nstreams;
     const uint64_t *ns, *out_off;    // out_off nullable (packed)
     uint64_t out_len;
@@ -96,7 +99,7 @@ int launch_b1_words(int bm, int dtype, const B1Args &a, uint64_t npairs, hipStre
 int launch_b1_batched(int bm, int dtype, int vi, const B1Args &a, uint32_t grid, hipStream_t s);
 // Polar: the mask, scan and generate kernels, in that order on stream s.
 // vm selects the value method: 0 = Algorithm P, 1 = method P2 (no trace
-// mode).  grid_mask / grid_gen are the persistent grid sizes of the first and
+// mode), 2 = Algorithm R (one output element per accepted candidate).  grid_mask / grid_gen are the persistent grid sizes of the first and
 // last.  part 0 launches all three, 1 the mask and scan kernels, 2 the
 // generate kernel.
 int launch_polar(int mode, int vm, int dtype, int vi, const PolarArgs &a, uint32_t grid_mask, uint32_t grid_gen,
@@ -110,19 +113,37 @@ int launch_probe_copy(void *dst, const void *src, uint64_t nbytes, uint32_t grid
 int launch_probe_hash(uint64_t seed, uint64_t nhash, uint64_t *sink, uint64_t sink_len, uint32_t grid,
                       hipStream_t s);
 
-// Candidate budget of a Polar stream of npairs accepted pairs, in words of
-// 64 candidates: the expected candidate count npairs / (pi/4), plus four
-// standard deviations of the negative-binomial count, plus 64.  Exceeding
-// the budget is not an error (the stream's last tile continues serially past
-// it); the budget only sizes the mask pass.
-__host__ __device__ inline uint64_t polar_budget_words(uint64_t npairs)
+// Candidate budget of a rejection stream that needs `need` accepted
+// candidates at acceptance probability p, in words of 64 candidates: the
+// expected candidate count need / p, plus four standard deviations of the
+// negative-binomial count, plus 64.  Exceeding the budget is not an error
+// (the stream's last tile continues serially past it); the budget only sizes
+// the mask pass.
+__host__ __device__ inline uint64_t candidate_budget_words(uint64_t need, double p)
 {
-    if (npairs == 0)
+    if (need == 0)
         return 0;
-    const double p = 0.78539816339744830962, q = 1.0 - p;
-    const double P = (double)npairs;
+    const double q = 1.0 - p;
+    const double P = (double)need;
     const double c = P / p + 4.0 * sqrt(P * q) / p + 64.0;
     return (uint64_t)(c / 64.0) + 1;
+}
+
+// Polar and P2: one accepted candidate per pair, p = pi/4.
+constexpr double kPolarAccept = 0.78539816339744830962;
+// Algorithm R: one accepted candidate per normal, p = sqrt(pi e)/4.
+constexpr double kRatioAccept = 0.73057059133056956;
+
+__host__ __device__ inline uint64_t polar_budget_words(uint64_t npairs)
+{
+    return candidate_budget_words(npairs, kPolarAccept);
+}
+
+// Budget of a stream of n normals for PrepArgs / PolarArgs method ids 1
+// (Polar), 2 (P2) and 4 (Algorithm R).
+__host__ __device__ inline uint64_t method_budget_words(int method, uint64_t n)
+{
+    return method == 4 ? candidate_budget_words(n, kRatioAccept) : polar_budget_words((n + 1) / 2);
 }
 
 }  // namespace nrng

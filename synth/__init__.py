@@ -131,6 +131,45 @@ def b3_edge_words(seed: int = 15) -> np.ndarray:
     return np.concatenate([arr, rnd])
 
 
+def ratio_edge_words(seed: int = 16) -> np.ndarray:
+    """Explicit 64-bit hash words for the Algorithm R test hook, two per
+    candidate (u-word, v-word; u = (w >> 11) 2^-53): u = 0 with several v;
+    u = 1 - 2^-53 with v = 1/2 + k 2^-53 for |k| <= 9 (there
+    x = sqrt(8/e) k and the test accepts exactly |k| <= 7); v = 1/2 and the
+    extreme v; points 1, 2 and 1024 units of v from the curve
+    x^2 = -4 ln(1 - u) on both sides, for random u; and random words."""
+    g = rng(seed)
+    H = 1 << 52                      # v = 1/2 in units of 2^-53
+
+    def w(k53):                      # word whose top 53 bits are k53
+        return np.uint64(int(k53) << 11)
+
+    rows = []
+    for vk in (0, H, H - 1, H + 1, (1 << 53) - 1, 3 * (1 << 51)):
+        rows.append((w(0), w(vk)))
+    top = (1 << 53) - 1              # u = 1 - 2^-53
+    for k in range(-9, 10):
+        rows.append((w(top), w(H + k)))
+    for k53 in (top - 1, top - 1000, (1 << 53) - (1 << 13), 3 * (1 << 51)):
+        rows.append((w(k53), w(H)))
+        rows.append((w(k53), w(0)))
+    c = math.sqrt(8.0 / math.e)
+    for uk in g.integers(0, 1 << 53, 48):
+        u = int(uk) * 2.0**-53
+        lim = math.sqrt(-4.0 * math.log1p(-u)) * (1.0 - u) / c    # |v - 1/2| on the curve
+        if lim >= 0.5:
+            continue
+        for sgn in (1, -1):
+            vb = int(round((0.5 + sgn * lim) * 2.0**53))
+            for d in (-1024, -2, -1, 0, 1, 2, 1024):
+                vk = vb + d
+                if 0 <= vk < (1 << 53):
+                    rows.append((w(uk), w(vk)))
+    arr = np.array(rows, dtype=np.uint64).reshape(-1)
+    rnd = g.integers(0, 2**64, 2 * 8192, dtype=np.uint64, endpoint=False)
+    return np.concatenate([arr, rnd])
+
+
 def polar2_edge_xy(seed: int = 14) -> np.ndarray:
     """Explicit int32 candidate pairs for the P2 test hook: the Polar edge
     points (which include the origin, accepted by P2), the origin repeated

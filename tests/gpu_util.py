@@ -39,6 +39,8 @@ def run(method: str, seed: int, offset: int, n: int, dtype: int, mu: float = 0.0
         nb.nrng_b3(seed, offset, n, mu, sigma, out, dtype)
     elif method == "polar2":
         nb.nrng_polar2(seed, offset, n, mu, sigma, out, dtype, None, cons)
+    elif method == "ratio":
+        nb.nrng_ratio(seed, offset, n, mu, sigma, out, dtype, None, cons)
     else:
         nb.nrng_polar(seed, offset, n, mu, sigma, out, dtype, None, cons)
     torch.cuda.synchronize()

@@ -7,8 +7,8 @@ the oracle computes independently:
   candidate chunks, placed by the oracle's own prefix of accepted counts,
   plus the consumed count;
 * the batched workload of 4096 streams (about 4.4e8 normals per method, B1,
-  Polar, P2 and B3): every stream's consumed count, and sampled streams in
-  full;
+  Polar, P2, B3 and Algorithm R): every stream's consumed count, and sampled
+  streams in full;
 * 64 graph-replayed fills of 2^28 FP32 Polar normals from one device cursor
   (2^34 normals of one stream): the final cursor against the oracle's count,
   and sampled slices of sampled fills, placed by the oracle's prefix, with
@@ -102,7 +102,8 @@ def test_polar_single_stream_2e30_sampled():
         assert_close(got, vals[:m], nb.NRNG_F32, what="polar 2^30 chunk %d" % c)
 
 
-@pytest.mark.parametrize("method", [nb.NRNG_METHOD_B1, nb.NRNG_METHOD_POLAR, nb.NRNG_METHOD_P2, nb.NRNG_METHOD_B3])
+@pytest.mark.parametrize("method", [nb.NRNG_METHOD_B1, nb.NRNG_METHOD_POLAR, nb.NRNG_METHOD_P2, nb.NRNG_METHOD_B3,
+                                    nb.NRNG_METHOD_R])
 def test_batched_full_workload_sampled(method):
     d = dev()
     cfg = synth.batched_streams()
@@ -126,14 +127,14 @@ def test_batched_full_workload_sampled(method):
     pick = sorted({int(order[0]), int(order[-1]), int(order[ns // 2])} |
                   set(synth.rng(33).integers(0, ns, 24).tolist()))
     fn = {nb.NRNG_METHOD_B1: O.b1, nb.NRNG_METHOD_POLAR: O.polar, nb.NRNG_METHOD_P2: O.polar2,
-          nb.NRNG_METHOD_B3: O.b3}[method]
+          nb.NRNG_METHOD_B3: O.b3, nb.NRNG_METHOD_R: O.ratio}[method]
     for j in pick:
         o0 = int(cfg["out_off"][j])
         ref, used = fn(int(cfg["seed"][j]), 0, int(n[j]), float(cfg["mu"][j]), float(cfg["sigma"][j]))
         assert int(c[j]) == used, j
         assert_close(host(out[o0:o0 + int(n[j])]), ref, nb.NRNG_F32, float(cfg["mu"][j]), float(cfg["sigma"][j]),
                      what="batched stream %d" % j)
-    if method in (nb.NRNG_METHOD_POLAR, nb.NRNG_METHOD_P2):
+    if method in (nb.NRNG_METHOD_POLAR, nb.NRNG_METHOD_P2, nb.NRNG_METHOD_R):
         # every stream's consumed count: at least the minimum 2 ceil(n/2),
         # even, and (for the sampled streams above) exactly the oracle's
         assert np.all(c >= (2 * ((n + 1) // 2)).astype(np.uint64)) and np.all(c % 2 == 0)
