@@ -63,16 +63,27 @@ VALU_PEAK_TOPS = 39.32
 #                   degree-9 Horner 9 + scaling 2 + the library branch's 9
 #                   operations for the 1/9 of pairs above 8/9 1 + split test and
 #                   select 2 + angle reduction, conversion, sin, cos 8 + 2 FMAs
+#   ratio_count:    per candidate: 2 hashes 36 + v - 1/2 and 1 - u as
+#                   integers 4 + their conversions (signed split 5, unsigned
+#                   3) 8 + x = c dv / du 3 + x^2 1 + -4 ln(1 - u) (scale, log,
+#                   scale) 3 + the comparison 1 + the FP32 screening band
+#                   (difference, sum, FMA, compare) 4; the FP64 test inside
+#                   the band (under 1e-4 of candidates) 0
+#   ratio_generate: per output: 2 hashes 36 + the integer differences 4 +
+#                   conversions 8 + x 3 + 1 FMA
 ALU_OPS = {"polar_count": 38, "polar_generate": 63, "b1_batched": 67, "p2_count": 37, "p2_generate": 58,
-           "b3_batched": 88}
+           "b3_batched": 88, "ratio_count": 60, "ratio_generate": 52}
 ALU_UNIT = {"polar_count": "candidate", "polar_generate": "output pair", "b1_batched": "output pair",
-            "p2_count": "candidate", "p2_generate": "output pair", "b3_batched": "output pair"}
+            "p2_count": "candidate", "p2_generate": "output pair", "b3_batched": "output pair",
+            "ratio_count": "candidate", "ratio_generate": "output"}
 KERNEL_NAMES = {"polar_count": "polar_mask_kernel<MODE_BATCHED> + polar_scan_kernel",
                 "polar_generate": "polar_gen_kernel<float, MODE_BATCHED>",
                 "b1_batched": "b1_batched_kernel<float>",
                 "p2_count": "polar_mask_kernel<MODE_BATCHED, VM_P2> + polar_scan_kernel",
                 "p2_generate": "polar_gen_kernel<float, MODE_BATCHED, VM_P2>",
-                "b3_batched": "b1_batched_kernel<float, BM_B3>"}
+                "b3_batched": "b1_batched_kernel<float, BM_B3>",
+                "ratio_count": "polar_mask_kernel<MODE_BATCHED, VM_R> + polar_scan_kernel",
+                "ratio_generate": "polar_gen_kernel<float, MODE_BATCHED, VM_R>"}
 PROFILES = os.path.join(ROOT, "profiles")
 
 
@@ -287,8 +298,7 @@ def extra_batched(nb, torch, stream, D, ns, total, pairs, steps, per_kernel, m):
     """Method P2 (Section 4), B3 (Section 3) or Algorithm R (Section 5) on the
     same batched workload, timed like the step's legs: plan, then exec part 1
     (P2, R: the mask and scan kernels; B3: nothing) and part 2 (the generate
-    kernel; the B3 kernel) between events.  R's mask kernel decides its test
-    in FP64, so no FP32 VALU fraction is given for it."""
+    kernel; the B3 kernel) between events."""
     out = torch.empty(total, dtype=torch.float32, device=D["n"].device)
     cons = torch.zeros(ns, dtype=torch.int64, device=D["n"].device)
 
@@ -324,9 +334,10 @@ def extra_batched(nb, torch, stream, D, ns, total, pairs, steps, per_kernel, m):
         units = {"p2_count": (count_ms, ALU_OPS["p2_count"] * cand),
                  "p2_generate": (gen_ms, ALU_OPS["p2_generate"] * pairs)}
     elif m == nb.NRNG_METHOD_R:
-        r.update({"count_ms": round(count_ms, 5), "generate_ms": round(gen_ms, 5),
-                  "candidates": int(u64sum(cons)) // 2})
-        units = {}
+        cand = int(u64sum(cons)) // 2
+        r.update({"count_ms": round(count_ms, 5), "generate_ms": round(gen_ms, 5), "candidates": cand})
+        units = {"ratio_count": (count_ms, ALU_OPS["ratio_count"] * cand),
+                 "ratio_generate": (gen_ms, ALU_OPS["ratio_generate"] * total)}
     else:
         r["consumed_uniforms"] = int(u64sum(cons))
         units = {"b3_batched": (gen_ms, ALU_OPS["b3_batched"] * pairs)}

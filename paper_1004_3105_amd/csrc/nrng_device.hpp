@@ -536,22 +536,51 @@ __device__ __forceinline__ double ratio_value_f64(uint64_t ku, uint64_t kv, doub
     return sigma * x + mu;
 }
 
-// FP32 value: x = c (v - 1/2)/(1 - u) = c dv / du with the 53-bit integers
+// FP32 x = c (v - 1/2)/(1 - u) = c dv / du with the 53-bit integers
 // dv = (k_v >> 11) - 2^52 and du = 2^53 - (k_u >> 11) >= 1 (the scale 2^-53
 // cancels), each converted with relative error below 2^-23; one reciprocal.
 // The signed dv is split at bit 21: the low part (below 2^21) converts
 // exactly and the high part exactly while |dv| < 2^45, so a small negative dv
 // (v just below 1/2, which matters when 1 - u is tiny) is not lost to a
-// rounded low word cancelling against the high one.
-__device__ __forceinline__ float ratio_value_f32(uint64_t ku, uint64_t kv, float c, float mu, float sigma)
+// rounded low word cancelling against the high one.  Also returns du as a
+// float (exactly representable scaling by 2^-53 gives 1 - u).
+__device__ __forceinline__ float ratio_x_f32(uint64_t ku, uint64_t kv, float c, float& fu)
 {
     const int64_t dv = (int64_t)(kv >> 11) - (1ll << 52);
     const uint64_t du = (1ull << 53) - (ku >> 11);
     const float fv = __builtin_fmaf(cvt_f32_i32((int32_t)(dv >> 21)), 0x1p21f,
                                     cvt_f32_u32((uint32_t)dv & 0x1FFFFFu));
-    const float fu = u64_to_f32_scaled(du, 0x1p32f, 1.0f);
-    const float x = c * fv * __builtin_amdgcn_rcpf(fu);
+    fu = u64_to_f32_scaled(du, 0x1p32f, 1.0f);
+    return c * fv * __builtin_amdgcn_rcpf(fu);
+}
+
+__device__ __forceinline__ float ratio_value_f32(uint64_t ku, uint64_t kv, float c, float mu, float sigma)
+{
+    float fu;
+    const float x = ratio_x_f32(ku, kv, c, fu);
     return __builtin_fmaf(sigma, x, mu);
+}
+
+// The acceptance test of ratio_accept, screened in FP32.  q = x^2 and
+// l = -4 ln(1 - u) = -4 ln 2 log2(du 2^-53) are formed in FP32: q has
+// relative error below 2^-19 (two conversions, the reciprocal's 1 ulp and
+// four roundings), and l absolute error below about 2^-21 (the conversion of
+// du moves log2 by at most 1.5 2^-23; v_log_f32 adds about an ulp) plus
+// 2^-23 l.  Where |q - l| exceeds 2^-14 (q + l) + 2^-17, at least 16 times
+// those bounds, the FP32 comparison is the FP64 one (whose own rounding is
+// some 2^-50 relative); inside that band (under 1e-4 of candidates) the
+// FP64 test decides.  Same decisions as ratio_accept, without its FP64
+// logarithm for nearly every wave.
+__device__ __forceinline__ bool ratio_accept_screened(uint64_t ku, uint64_t kv, double c, float c32)
+{
+    float fu;
+    const float x = ratio_x_f32(ku, kv, c32, fu);
+    const float q = x * x;
+    const float l = -2.7725887222397812f * __builtin_amdgcn_logf(fu * 0x1p-53f);
+    bool acc = q <= l;
+    if (__builtin_fabsf(q - l) <= __builtin_fmaf(0x1p-14f, q + l, 0x1p-17f))
+        acc = ratio_accept(ku, kv, c);
+    return acc;
 }
 
 // ---------------------------------------------------------------------------

@@ -137,7 +137,9 @@ def ratio_edge_words(seed: int = 16) -> np.ndarray:
     u = 1 - 2^-53 with v = 1/2 + k 2^-53 for |k| <= 9 (there
     x = sqrt(8/e) k and the test accepts exactly |k| <= 7); v = 1/2 and the
     extreme v; points 1, 2 and 1024 units of v from the curve
-    x^2 = -4 ln(1 - u) on both sides, for random u; and random words."""
+    x^2 = -4 ln(1 - u) on both sides, for random u, and 2^k units away for
+    k = 3, 6, ..., 45 (this spans the whole width of any FP32 screening band
+    around the curve); and random words."""
     g = rng(seed)
     H = 1 << 52                      # v = 1/2 in units of 2^-53
 
@@ -154,14 +156,14 @@ def ratio_edge_words(seed: int = 16) -> np.ndarray:
         rows.append((w(k53), w(H)))
         rows.append((w(k53), w(0)))
     c = math.sqrt(8.0 / math.e)
-    for uk in g.integers(0, 1 << 53, 48):
+    for uk in g.integers(0, 1 << 53, 96):
         u = int(uk) * 2.0**-53
         lim = math.sqrt(-4.0 * math.log1p(-u)) * (1.0 - u) / c    # |v - 1/2| on the curve
         if lim >= 0.5:
             continue
         for sgn in (1, -1):
             vb = int(round((0.5 + sgn * lim) * 2.0**53))
-            for d in (-1024, -2, -1, 0, 1, 2, 1024):
+            for d in (-1024, -2, -1, 0, 1, 2, 1024) + tuple(sg * (1 << k) for k in range(3, 46, 3) for sg in (1, -1)):
                 vk = vb + d
                 if 0 <= vk < (1 << 53):
                     rows.append((w(uk), w(vk)))
