@@ -17,7 +17,7 @@ graph-replayed repeated fill (64 x 2^28 Polar normals), methods P2 (Section
 and the CPU oracle timed on the host cores.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extras]
-                       [--no-cpu] [--only b1|polar]
+                       [--no-cpu] [--only b1|polar|p2|b3|ratio]
 """
 from __future__ import annotations
 
@@ -132,9 +132,10 @@ def main() -> int:
     ap.add_argument("--nstreams", type=int, default=4096)
     ap.add_argument("--no-extras", action="store_true", help="skip the side measurements")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--only", choices=["b1", "polar", "p2"], default=None,
-                    help="time one method only (for profiling runs; p2 = method P2 of Section 4, which is "
-                         "otherwise measured among the extras)")
+    ap.add_argument("--only", choices=["b1", "polar", "p2", "b3", "ratio"], default=None,
+                    help="time one method only (for profiling runs; p2, b3 and ratio = method P2 of Section 4, "
+                         "method B3 of Section 3 and Algorithm R of Section 5, which are otherwise measured "
+                         "among the extras)")
     ap.add_argument("--calibrate", action="store_true",
                     help="also run a 1 GiB copy and a 1 GiB store probe once (known traffic, for scaling "
                          "hardware byte counters in profiling runs)")
@@ -172,8 +173,9 @@ def main() -> int:
         "sigma": torch.from_numpy(cfg["sigma"]).to(dev),
     }
     methods = [("b1", nb.NRNG_METHOD_B1), ("polar", nb.NRNG_METHOD_POLAR)]
-    if args.only == "p2":
-        methods = [("p2", nb.NRNG_METHOD_P2)]
+    extra_methods = {"p2": nb.NRNG_METHOD_P2, "b3": nb.NRNG_METHOD_B3, "ratio": nb.NRNG_METHOD_R}
+    if args.only in extra_methods:
+        methods = [(args.only, extra_methods[args.only])]
     elif args.only:
         methods = [m for m in methods if m[0] == args.only]
     outs = {name: torch.empty(total, dtype=torch.float32, device=dev) for name, _ in methods}
@@ -223,15 +225,16 @@ def main() -> int:
         per_kernel[name] = {"plan_ms": round(plan_ms, 5), "exec_ms": round(exec_ms, 5),
                             "normals_per_s": total / (exec_ms * 1e-3), "write_GBps": round(gbs, 1),
                             "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)}
-        if name in ("polar", "p2"):
+        if name in ("polar", "p2", "ratio"):
             cand = int(u64sum(cons[name])) // 2       # candidates the method evaluates
             per_kernel[name]["count_ms"] = round(count_ms, 5)
             per_kernel[name]["generate_ms"] = round(gen_ms, 5)
             per_kernel[name]["candidates"] = cand
+            gen_units = total if name == "ratio" else pairs    # R yields one normal per candidate
             units = {name + "_count": (count_ms, ALU_OPS[name + "_count"] * cand),
-                     name + "_generate": (gen_ms, ALU_OPS[name + "_generate"] * pairs)}
+                     name + "_generate": (gen_ms, ALU_OPS[name + "_generate"] * gen_units)}
         else:
-            units = {"b1_batched": (gen_ms, ALU_OPS["b1_batched"] * pairs)}
+            units = {name + "_batched": (gen_ms, ALU_OPS[name + "_batched"] * pairs)}
         for k, (ms, ops) in units.items():
             per_kernel[name].setdefault("alu", {})[k] = {
                 "ms": round(ms, 5), "Tops_per_s": round(ops / (ms * 1e-3) / 1e12, 2),
@@ -281,13 +284,10 @@ def main() -> int:
         del src, dst
     if not args.no_extras:
         result["extras"] = extras(nb, torch, dev, stream, per_kernel, value)
-        if args.only != "p2":
-            result["extras"]["p2_batched"] = extra_batched(nb, torch, stream, D, ns, total, pairs, args.steps,
-                                                           per_kernel, nb.NRNG_METHOD_P2)
-        result["extras"]["b3_batched"] = extra_batched(nb, torch, stream, D, ns, total, pairs, args.steps,
-                                                       per_kernel, nb.NRNG_METHOD_B3)
-        result["extras"]["ratio_batched"] = extra_batched(nb, torch, stream, D, ns, total, pairs, args.steps,
-                                                          per_kernel, nb.NRNG_METHOD_R)
+        for name, m in extra_methods.items():
+            if args.only != name:
+                result["extras"][name + "_batched"] = extra_batched(nb, torch, stream, D, ns, total, pairs,
+                                                                    args.steps, per_kernel, m)
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(cfg, [m for m, _ in methods])
     print(json.dumps(result), flush=True)
@@ -450,7 +450,7 @@ def cpu_baseline(cfg, methods):
 
     def work(mj):
         m, j = mj
-        fn = {"b1": O.b1, "polar": O.polar, "p2": O.polar2}[m]
+        fn = {"b1": O.b1, "polar": O.polar, "p2": O.polar2, "b3": O.b3, "ratio": O.ratio}[m]
         fn(int(cfg["seed"][j]), int(cfg["offset"][j]), int(cfg["n"][j]), float(cfg["mu"][j]), float(cfg["sigma"][j]))
         return int(cfg["n"][j])
 
