@@ -4,7 +4,7 @@ This package wraps ``nrng_oracle.c`` -- a plain single-threaded C99
 implementation, in IEEE double precision without fused multiply-add, of
 Box-Muller Algorithm B1 and the Polar method (Algorithm P) from Section 2 of
 Brent's "Fast Normal Random Number Generators for Vector Processors" (1993),
-method B3 of its Section 3, method P2 of its Section 4 and Algorithm R of
+methods B2 and B3 of its Section 3, method P2 of its Section 4 and Algorithm R of
 its Section 5, fed by a counter-based SplitMix64 uniform stream.
 
 Only the test suite, the smoke check and the CPU-baseline leg of the
@@ -77,6 +77,11 @@ def lib():
                 "orc_polar2": (u64, [u64, u64, u64, f64, f64, vp]),
                 "orc_polar2_count": (u64, [u64, u64, u64]),
                 "orc_polar2_window": (u64, [u64, u64, u64, u64, f64, f64, vp]),
+                "orc_b2_coef": (None, [vp, vp]),
+                "orc_b2_sincos": (None, [f64, vp, vp]),
+                "orc_b2_uv": (None, [vp, vp, u64, f64, f64, vp]),
+                "orc_b2_words": (None, [vp, u64, f64, f64, vp]),
+                "orc_b2": (u64, [u64, u64, u64, f64, f64, vp]),
                 "orc_b3_u": (None, [vp, vp, vp, u64, f64, f64, vp]),
                 "orc_b3_words": (None, [vp, u64, f64, f64, vp]),
                 "orc_b3": (u64, [u64, u64, u64, f64, f64, vp]),
@@ -318,6 +323,47 @@ def polar2_window(seed: int, offset: int, j0: int, ncand: int, mu: float = 0.0, 
     out = np.empty(max(2 * ncand, 1), dtype=np.float64)
     a = int(lib().orc_polar2_window(seed & M64, offset & M64, j0, ncand, mu, sigma, _p(out)))
     return out[:2 * a]
+
+
+# ---------------------------------------------------------------- B2
+def b2_coef():
+    """(s1, s3, s5, s7) and (c0, c2, c4, c6) of method B2's sine and cosine."""
+    s = np.empty(4, dtype=np.float64)
+    c = np.empty(4, dtype=np.float64)
+    lib().orc_b2_coef(_p(s), _p(c))
+    return s, c
+
+
+def b2_sincos(v: float):
+    """B2's approximations to sin(2 pi v - pi) and cos(2 pi v - pi)."""
+    sn = np.empty(1, dtype=np.float64)
+    cs = np.empty(1, dtype=np.float64)
+    lib().orc_b2_sincos(float(v), _p(sn), _p(cs))
+    return float(sn[0]), float(cs[0])
+
+
+def b2(seed: int, offset: int, n: int, mu: float = 0.0, sigma: float = 1.0):
+    """n normals by method B2; returns (values, uniforms consumed)."""
+    out = np.empty(max(n, 1), dtype=np.float64)
+    used = lib().orc_b2(seed & M64, offset & M64, n, mu, sigma, _p(out))
+    return out[:n], int(used)
+
+
+def b2_uv(u, v, mu: float = 0.0, sigma: float = 1.0) -> np.ndarray:
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    assert u.shape == v.shape
+    out = np.empty(2 * u.size, dtype=np.float64)
+    lib().orc_b2_uv(_p(u), _p(v), u.size, mu, sigma, _p(out))
+    return out
+
+
+def b2_words(words, mu: float = 0.0, sigma: float = 1.0) -> np.ndarray:
+    w = np.ascontiguousarray(words, dtype=np.uint64)
+    assert w.size % 2 == 0
+    out = np.empty(w.size, dtype=np.float64)
+    lib().orc_b2_words(_p(w), w.size // 2, mu, sigma, _p(out))
+    return out
 
 
 # ---------------------------------------------------------------- B3

@@ -1,7 +1,7 @@
 /*
  * nrng_oracle.c -- plain, slow, single-threaded FP64 reference for the
  * normal-deviate path: Box-Muller Algorithm B1 and the Polar method,
- * Algorithm P (Section 2), method B3 (Section 3), method P2 (Section 4,
+ * Algorithm P (Section 2), methods B2 and B3 (Section 3), method P2 (Section 4,
  * the Polar method with the radius factor of method B3) and Algorithm R
  * (Section 5, the ratio method in its basic form) of Brent, "Fast Normal Random
  * Number Generators for Vector Processors", 1993.
@@ -17,9 +17,10 @@
  * multiply-add, so every line below is one IEEE-754 double operation).
  *
  * Pins (see the tests): the SplitMix64 check sequence, closed-form B1,
- * Polar, P2 and B3 values for chosen inputs, the paper's error bound of the P2
- * polynomial against the closed form, brute-force lattice counts of the Polar
- * acceptance predicate on small grids, the pi/4 acceptance rate, the
+ * Polar, P2, B2, B3 and R values for chosen inputs, the paper's error
+ * bounds of the P2 polynomial and of B2's sine and cosine against the
+ * closed forms, brute-force lattice counts of the Polar acceptance predicate
+ * on small grids, the pi/4 and sqrt(pi e)/4 acceptance rates, the
  * uniformity of the accepted s, sample moments and a Kolmogorov-Smirnov
  * statistic against the normal CDF.
  */
@@ -526,6 +527,169 @@ uint64_t orc_b3(uint64_t seed, uint64_t offset, uint64_t n, double mu, double si
             out[2 * k + 1] = y;
     }
     return 3 * npairs;
+}
+
+/* ------------------------------------------------------------------------
+ * Method B2, Section 3: Algorithm B1 with the library sine and cosine
+ * replaced by an inline approximation.  With the angle 2 pi v - pi and
+ * y = (2 pi v - pi)/16, so |y| <= pi/16:
+ *   sin y ~= s1 y + s3 y^3 + s5 y^5 + s7 y^7,
+ *   cos y ~= c0 + c2 y^2 + c4 y^4 + c6 y^6,
+ * and four angle doublings, sin 2y = 2 sin y cos y and
+ * cos 2y = 1 - 2 sin^2 y, give sin 16y and cos 16y.  The rest is B1:
+ * r = sigma sqrt(-2 ln(1 - u)), outputs r sin(16y) + mu, then
+ * r cos(16y) + mu; pair k takes uniforms 2k and 2k + 1.
+ *
+ * The paper prints neither the coefficients nor their construction, only
+ * that the approximations keep the absolute error well below 1e-10.  They
+ * are taken here as the Chebyshev series of sin(y)/y and of cos y, as
+ * functions of t = y^2 on [0, (pi/16)^2], truncated after T_3 (the
+ * construction Section 3 uses for h), and written in powers of t.  The
+ * polynomials are evaluated in the nested form y (s1 + t (s3 + t (s5 + t s7)))
+ * and c0 + t (c2 + t (c4 + t c6)).
+ * --------------------------------------------------------------------- */
+#define B2_TAYLOR 14
+
+static long double b2_binom(int n, int k)
+{
+    long double r = 1.0L;
+    for (int i = 1; i <= k; ++i)
+        r = r * (long double)(n - k + i) / (long double)i;
+    return r;
+}
+
+/* The truncated series, computed from the Taylor series f(t) = sum_n f_n t^n
+ * term by term (the truncation is linear): with t = (tmax/2)(x + 1) on
+ * x in [-1, 1], (x + 1)^n = sum_j C(n, j) x^j and
+ * x^j = 2^(1-j) sum_i C(j, i) T_{j-2i}(x) (the T_0 term halved); the terms
+ * above T_3 are dropped, the rest is written in powers of x
+ * (T_2 = 2x^2 - 1, T_3 = 4x^3 - 3x) and then of t (x = al t - 1,
+ * al = 2/tmax).  Each small coefficient is thus a sum of small terms, not
+ * the difference of large ones.  Taylor terms past B2_TAYLOR are below
+ * 1e-60 on [0, tmax]. */
+static void b2_series(const long double *fn, long double tmax, double *m)
+{
+    const long double al = 2.0L / tmax;
+    long double acc[4] = {0.0L, 0.0L, 0.0L, 0.0L};
+    long double scale = 1.0L;                       /* (tmax/2)^n */
+    for (int n = 0; n < B2_TAYLOR; ++n) {
+        long double b[4] = {0.0L, 0.0L, 0.0L, 0.0L};   /* T_0..T_3 part of (x + 1)^n */
+        for (int j = 0; j <= n; ++j) {
+            for (int i = 0; 2 * i <= j; ++i) {
+                int k = j - 2 * i;
+                if (k > 3)
+                    continue;
+                long double w = ldexpl(b2_binom(j, i), 1 - j);
+                if (k == 0)
+                    w *= 0.5L;
+                b[k] += b2_binom(n, j) * w;
+            }
+        }
+        long double p[4] = {b[0] - b[2], b[1] - 3.0L * b[3], 2.0L * b[2], 4.0L * b[3]};
+        long double ali = 1.0L;
+        for (int i = 0; i < 4; ++i) {
+            long double sum = 0.0L;
+            for (int j = i; j < 4; ++j)
+                sum += p[j] * b2_binom(j, i) * (((j - i) & 1) ? -1.0L : 1.0L);
+            acc[i] += fn[n] * scale * ali * sum;
+            ali *= al;
+        }
+        scale *= 0.5L * tmax;
+    }
+    for (int i = 0; i < 4; ++i)
+        m[i] = (double)acc[i];
+}
+
+/* s[0..3] = s1, s3, s5, s7 and c[0..3] = c0, c2, c4, c6. */
+void orc_b2_coef(double *s, double *c)
+{
+    const long double pi = 3.141592653589793238462643383279502884L;
+    const long double tmax = (pi / 16.0L) * (pi / 16.0L);
+    /* sin(y)/y = sum_n (-1)^n t^n / (2n + 1)!,  cos y = sum_n (-1)^n t^n / (2n)! */
+    long double fs[B2_TAYLOR], fc[B2_TAYLOR];
+    long double fact = 1.0L;                        /* (2n)! */
+    for (int n = 0; n < B2_TAYLOR; ++n) {
+        if (n > 0)
+            fact *= (long double)(2 * n - 1) * (long double)(2 * n);
+        long double sg = (n & 1) ? -1.0L : 1.0L;
+        fc[n] = sg / fact;
+        fs[n] = sg / (fact * (long double)(2 * n + 1));
+    }
+    b2_series(fs, tmax, s);
+    b2_series(fc, tmax, c);
+}
+
+/* sin(16y) and cos(16y) from the polynomials at y and four doublings. */
+static void b2_sincos16(const double *s, const double *c, double y, double *sn, double *cs)
+{
+    double t = y * y;
+    double sv = y * (s[0] + t * (s[1] + t * (s[2] + t * s[3])));
+    double cv = c[0] + t * (c[1] + t * (c[2] + t * c[3]));
+    for (int i = 0; i < 4; ++i) {
+        double s2 = 2.0 * sv * cv;
+        cv = 1.0 - 2.0 * sv * sv;
+        sv = s2;
+    }
+    *sn = sv;
+    *cs = cv;
+}
+
+/* The approximations to sin(2 pi v - pi) and cos(2 pi v - pi). */
+void orc_b2_sincos(double v, double *sn, double *cs)
+{
+    double s[4], c[4];
+    orc_b2_coef(s, c);
+    b2_sincos16(s, c, ((2.0 * M_PI) * v - M_PI) / 16.0, sn, cs);
+}
+
+static void b2_pair(const double *s, const double *c, double u, double v, double mu, double sigma, double *x,
+                    double *y)
+{
+    double r = sigma * sqrt(-2.0 * log(1.0 - u));
+    double sn, cs;
+    b2_sincos16(s, c, ((2.0 * M_PI) * v - M_PI) / 16.0, &sn, &cs);
+    *x = r * sn + mu;
+    *y = r * cs + mu;
+}
+
+/* B2 from explicit uniforms: pair p uses (u[p], v[p]). */
+void orc_b2_uv(const double *u, const double *v, uint64_t npairs, double mu, double sigma, double *out)
+{
+    double s[4], c[4];
+    orc_b2_coef(s, c);
+    for (uint64_t p = 0; p < npairs; ++p)
+        b2_pair(s, c, u[p], v[p], mu, sigma, &out[2 * p], &out[2 * p + 1]);
+}
+
+/* B2 from explicit 64-bit hash words, two per pair: u = (w >> 11) 2^-53. */
+void orc_b2_words(const uint64_t *w, uint64_t npairs, double mu, double sigma, double *out)
+{
+    double s[4], c[4];
+    orc_b2_coef(s, c);
+    for (uint64_t p = 0; p < npairs; ++p) {
+        double u = (double)(w[2 * p] >> 11) * 0x1p-53;
+        double v = (double)(w[2 * p + 1] >> 11) * 0x1p-53;
+        b2_pair(s, c, u, v, mu, sigma, &out[2 * p], &out[2 * p + 1]);
+    }
+}
+
+/* B2 over the counter stream: n values; returns the uniforms consumed,
+ * 2 ceil(n/2). */
+uint64_t orc_b2(uint64_t seed, uint64_t offset, uint64_t n, double mu, double sigma, double *out)
+{
+    double s[4], c[4];
+    orc_b2_coef(s, c);
+    uint64_t npairs = (n + 1) / 2;
+    for (uint64_t k = 0; k < npairs; ++k) {
+        double u = orc_uniform(seed, offset + 2 * k);
+        double v = orc_uniform(seed, offset + 2 * k + 1);
+        double x, y;
+        b2_pair(s, c, u, v, mu, sigma, &x, &y);
+        out[2 * k] = x;
+        if (2 * k + 1 < n)
+            out[2 * k + 1] = y;
+    }
+    return 2 * npairs;
 }
 
 /* ------------------------------------------------------------------------

@@ -42,6 +42,12 @@ uint64_t orc_polar2_count(uint64_t seed, uint64_t offset, uint64_t ncand);
 uint64_t orc_polar2_window(uint64_t seed, uint64_t offset, uint64_t j0, uint64_t ncand, double mu,
                            double sigma, double *out);
 
+void orc_b2_coef(double *s, double *c);
+void orc_b2_sincos(double v, double *sn, double *cs);
+void orc_b2_uv(const double *u, const double *v, uint64_t npairs, double mu, double sigma, double *out);
+void orc_b2_words(const uint64_t *w, uint64_t npairs, double mu, double sigma, double *out);
+uint64_t orc_b2(uint64_t seed, uint64_t offset, uint64_t n, double mu, double sigma, double *out);
+
 void orc_b3_u(const double *u1, const double *u2, const double *u3, uint64_t npairs, double mu, double sigma,
               double *out);
 void orc_b3_words(const uint64_t *w, uint64_t npairs, double mu, double sigma, double *out);

@@ -29,6 +29,11 @@ What pins what:
     order cos then sin, the shift by -pi, both sides of 8/9), the whole
     stream pair by pair against sqrt(-2 log1p(-m^2)) (cos t, sin t)
     computed here, 3 uniforms per pair, and the distribution;
+  * method B2 (Section 3): closed-form values (the angle 2 pi v - pi, the
+    factor 16, the order sin then cos), the paper's error bound on the inline
+    sine and cosine against the library (which Taylor coefficients would
+    miss), the error's orthogonality to T_0 .. T_3 (the truncated Chebyshev
+    series), B2 == -B1 pair by pair, and the stream and distribution;
   * Algorithm R (Section 5): closed-form accept/reject cases on both sides
     of the curve x^2 = -4 ln(1 - u), the acceptance rate sqrt(pi e)/4 (the
     2.74 uniforms per normal the section states), the stream's composition,
@@ -390,6 +395,98 @@ def check_polar2_distribution(n: int = 1 << 20):
 
 
 # ------------------------------------------------------------------ B3
+def check_b2_hand():
+    rows = golden_rows("b2_hand_values.txt")
+    u = np.array([closed_form(r[0]) for r in rows])
+    v = np.array([closed_form(r[1]) for r in rows])
+    out = O.b2_uv(u, v).reshape(-1, 2)
+    for k, r in enumerate(rows):
+        kind, amt = r[4].split(":")
+        for c in range(2):
+            want, got = closed_form(r[2 + c]), out[k, c]
+            if kind == "abs" or want == 0.0:
+                assert abs(got - want) <= float(amt), (r, c, got, want)
+            else:
+                assert ulp_dist64([got], [want])[0] <= int(amt), (r, c, got, want)
+    w = np.stack([(np.round(u * 2.0**53).astype(np.uint64) << np.uint64(11)),
+                  (np.round(v * 2.0**53).astype(np.uint64) << np.uint64(11))], axis=1).reshape(-1)
+    assert np.array_equal(O.b2_words(w), out.reshape(-1))
+    out2 = O.b2_uv(u, v, mu=-2.0, sigma=0.5)
+    assert np.allclose(out2, -2.0 + 0.5 * out.reshape(-1), rtol=0, atol=1e-14)
+
+
+def check_b2_bound():
+    """Section 3 puts the error of B2's inline sine and cosine well below
+    1e-10 in absolute terms; the degree-7/6 near-minimax polynomials with
+    four doublings reach about 2e-12 (Taylor coefficients would give 2.4e-10).
+    The coefficients are the truncated Chebyshev series: the error of each
+    polynomial is orthogonal to T_0 .. T_3 under the Chebyshev weight
+    (checked by Gauss-Chebyshev quadrature), and they are close to the Taylor
+    coefficients of sin and cos."""
+    v = np.concatenate([np.linspace(0.0, 1.0, 20001)[:-1], np.random.Generator(np.random.PCG64(21)).uniform(0.0, 1.0, 20000)])
+    err = 0.0
+    for x in v:
+        sn, cs = O.b2_sincos(float(x))
+        th = 2.0 * math.pi * float(x) - math.pi
+        err = max(err, abs(sn - math.sin(th)), abs(cs - math.cos(th)))
+    assert err < 1e-11, err
+    assert err > 1e-13, err                    # an approximation, not the library
+    s, c = O.b2_coef()
+    taylor_s = [1.0, -1.0 / 6, 1.0 / 120, -1.0 / 5040]
+    taylor_c = [1.0, -0.5, 1.0 / 24, -1.0 / 720]
+    for got, tay in zip(list(s) + list(c), taylor_s + taylor_c):
+        assert abs(got - tay) <= 2e-3 * abs(tay), (got, tay)
+    tmax = (math.pi / 16) ** 2
+    N = 64
+    xj = np.cos(math.pi * (np.arange(N) + 0.5) / N)
+    t = tmax * (xj + 1) / 2
+    y = np.sqrt(t)
+    for f, coef in ((np.sin(y) / y, s), (np.cos(y), c)):
+        p = coef[0] + t * (coef[1] + t * (coef[2] + t * coef[3]))
+        e = f - p
+        for k in range(4):
+            resid = abs(np.sum(e * np.cos(k * np.arccos(xj)))) / N
+            assert resid < 1e-3 * np.max(np.abs(e)), (k, resid, np.max(np.abs(e)))
+
+
+def check_b2_vs_b1():
+    """B2's angle is B1's minus pi, on the same uniforms and radius, so pair
+    k of B2 is pair k of B1 negated (about mu) up to the approximation."""
+    seed, off, n = 0xB2, 5, 40000
+    for mu, sigma in ((0.0, 1.0), (3.0, 0.25)):
+        z2, c2 = O.b2(seed, off, n, mu, sigma)
+        z1, c1 = O.b1(seed, off, n, mu, sigma)
+        assert c1 == c2 == n
+        d2, d1 = (z2 - mu).reshape(-1, 2), (z1 - mu).reshape(-1, 2)
+        r = np.hypot(d1[:, 0], d1[:, 1])
+        assert np.all(np.abs(d2 + d1) <= 4e-12 * r[:, None] + 1e-15), np.max(np.abs(d2 + d1))
+        assert np.allclose(np.hypot(d2[:, 0], d2[:, 1]), r, rtol=1e-11, atol=0)
+
+
+def check_b2_stream():
+    # pair k takes uniforms 2k, 2k + 1; the stream equals the explicit-uniform
+    # and explicit-word forms; n odd keeps the first value; restarting at
+    # offset + consumed continues it
+    seed, off, n = 0xB2B2, 33, 30001
+    z, used = O.b2(seed, off, n)
+    assert used == 2 * ((n + 1) // 2)
+    u = O.uniforms(seed, off, used).reshape(-1, 2)
+    ref = O.b2_uv(u[:, 0], u[:, 1])
+    assert np.array_equal(z, ref[:n])
+    assert np.array_equal(O.b2_words(O.hashes(seed, off, used))[:n], ref[:n])
+    z1, c1 = O.b2(seed, off, 1000)
+    z2, c2 = O.b2(seed, off + c1, n - 1000)
+    assert np.array_equal(np.concatenate([z1, z2]), z) and c1 + c2 == used
+
+
+def check_b2_distribution(n: int = 1 << 20):
+    z, _ = O.b2(1, 0, n)
+    _dist_checks(z)
+    from scipy import stats
+    ang = np.arctan2(z[0::2], z[1::2]) / (2 * math.pi) % 1.0
+    assert stats.kstest(ang, "uniform").statistic < 1.95 / math.sqrt(ang.size)
+
+
 def check_b3_hand():
     rows = golden_rows("b3_hand_values.txt")
     u1 = np.array([closed_form(r[0]) for r in rows])
@@ -551,6 +648,7 @@ ALL_CHECKS = [
     check_b1_composition, check_polar_hand, check_polar_lattice, check_polar_composition,
     check_polar_accept_rate, check_polar_s_uniform, check_b1_distribution, check_polar_distribution,
     check_stats_routines, check_p2_poly_bound, check_polar2_hand, check_polar2_lattice, check_polar2_vs_polar,
-    check_polar2_distribution, check_b3_hand, check_b3_stream, check_b3_distribution, check_ratio_hand,
+    check_polar2_distribution, check_b2_hand, check_b2_bound, check_b2_vs_b1, check_b2_stream,
+    check_b2_distribution, check_b3_hand, check_b3_stream, check_b3_distribution, check_ratio_hand,
     check_ratio_rate, check_ratio_stream, check_ratio_distribution,
 ]

@@ -67,6 +67,20 @@ MUTANTS = {
     "p2_consumed": ("            polar2_value(c, X, Y, mu, sigma, &zx, &zy);\n            out[written++] = zx;\n            if (written < n)\n                out[written++] = zy;\n        }\n        ++j;\n    }\n    return 2 * j;",
                     "            polar2_value(c, X, Y, mu, sigma, &zx, &zy);\n            out[written++] = zx;\n            if (written < n)\n                out[written++] = zy;\n        }\n        ++j;\n    }\n    return 2 * j + 2;"),
     "p2_sigma": ("r = sigma * cheb_sum(c, P2_DEGREE, v);", "r = cheb_sum(c, P2_DEGREE, v);"),
+    "b2_taylor": ("#define B2_TAYLOR 14", "#define B2_TAYLOR 4"),
+    "b2_three_doublings": ("    for (int i = 0; i < 4; ++i) {\n        double s2", "    for (int i = 0; i < 3; ++i) {\n        double s2"),
+    "b2_cos_new_s": ("        cv = 1.0 - 2.0 * sv * sv;\n        sv = s2;", "        sv = s2;\n        cv = 1.0 - 2.0 * sv * sv;"),
+    "b2_t_not_squared": ("    double t = y * y;\n    double sv = y *", "    double t = y;\n    double sv = y *"),
+    "b2_eighth": ("b2_sincos16(s, c, ((2.0 * M_PI) * v - M_PI) / 16.0, &sn, &cs);", "b2_sincos16(s, c, ((2.0 * M_PI) * v - M_PI) / 8.0, &sn, &cs);"),
+    "b2_no_shift": ("b2_sincos16(s, c, ((2.0 * M_PI) * v - M_PI) / 16.0, &sn, &cs);", "b2_sincos16(s, c, ((2.0 * M_PI) * v) / 16.0, &sn, &cs);"),
+    "b2_swap": ("    *x = r * sn + mu;\n    *y = r * cs + mu;", "    *x = r * cs + mu;\n    *y = r * sn + mu;"),
+    "b2_cheb_t0": ("                if (k == 0)\n                    w *= 0.5L;", "                if (k == 0)\n                    w *= 1.0L;"),
+    "b2_binom_sign": ("sum += p[j] * b2_binom(j, i) * (((j - i) & 1) ? -1.0L : 1.0L);", "sum += p[j] * b2_binom(j, i);"),
+    "b2_sigma": ("    double r = sigma * sqrt(-2.0 * log(1.0 - u));\n    double sn, cs;", "    double r = sqrt(-2.0 * log(1.0 - u));\n    double sn, cs;"),
+    "b2_consumed": ("        b2_pair(s, c, u, v, mu, sigma, &x, &y);\n        out[2 * k] = x;\n        if (2 * k + 1 < n)\n            out[2 * k + 1] = y;\n    }\n    return 2 * npairs;",
+                    "        b2_pair(s, c, u, v, mu, sigma, &x, &y);\n        out[2 * k] = x;\n        if (2 * k + 1 < n)\n            out[2 * k + 1] = y;\n    }\n    return 2 * npairs + 2;"),
+    "b2_pairing": ("        double u = orc_uniform(seed, offset + 2 * k);\n        double v = orc_uniform(seed, offset + 2 * k + 1);\n        double x, y;\n        b2_pair(",
+                   "        double v = orc_uniform(seed, offset + 2 * k);\n        double u = orc_uniform(seed, offset + 2 * k + 1);\n        double x, y;\n        b2_pair("),
     "b3_min": ("double m = u1 > u2 ? u1 : u2;", "double m = u1 < u2 ? u1 : u2;"),
     "b3_u_is_m": ("    double u = m * m;\n    double r;\n    if (u > 8.0 / 9.0) {\n        r = sigma * sqrt(-log(1.0 - u));",
                   "    double u = m;\n    double r;\n    if (u > 8.0 / 9.0) {\n        r = sigma * sqrt(-log(1.0 - u));"),
