@@ -13,11 +13,11 @@ Alongside, outside the timed region: the measured store-only and hash-only
 ceilings, the single-stream fills of 2^30 normals (FP32, BF16, FP16 and the
 plain FP64 kernels, the comparison point of the FP32 batched figure), the
 graph-replayed repeated fill (64 x 2^28 Polar normals), methods P2 (Section
-4), B3 (Section 3) and Algorithm R (Section 5) on the same batched workload,
-and the CPU oracle timed on the host cores.
+4), B3 and B2 (Section 3) and Algorithm R (Section 5) on the same batched
+workload, and the CPU oracle timed on the host cores.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extras]
-                       [--no-cpu] [--only b1|polar|p2|b3|ratio]
+                       [--no-cpu] [--only b1|polar|p2|b3|ratio|b2]
 """
 from __future__ import annotations
 
@@ -71,11 +71,16 @@ VALU_PEAK_TOPS = 39.32
 #                   the band (under 1e-4 of candidates) 0
 #   ratio_generate: per output: 2 hashes 36 + the integer differences 4 +
 #                   conversions 8 + x 3 + 1 FMA
+#   b2_batched:     per pair: hash of u 18 + hash of v (top word) 17 +
+#                   ln(1 - u) with the exact complement 21 + quarter-turn
+#                   reduction, conversion and scaling of y 6 + t = y^2 and
+#                   the two polynomials (6 FMAs, 1 product) 8 + four
+#                   doublings (d = 2s, s' = d c, c' = 1 - d s) 12 + 2 FMAs
 ALU_OPS = {"polar_count": 38, "polar_generate": 63, "b1_batched": 67, "p2_count": 37, "p2_generate": 58,
-           "b3_batched": 88, "ratio_count": 60, "ratio_generate": 52}
+           "b3_batched": 88, "ratio_count": 60, "ratio_generate": 52, "b2_batched": 84}
 ALU_UNIT = {"polar_count": "candidate", "polar_generate": "output pair", "b1_batched": "output pair",
             "p2_count": "candidate", "p2_generate": "output pair", "b3_batched": "output pair",
-            "ratio_count": "candidate", "ratio_generate": "output"}
+            "ratio_count": "candidate", "ratio_generate": "output", "b2_batched": "output pair"}
 KERNEL_NAMES = {"polar_count": "polar_mask_kernel<MODE_BATCHED> + polar_scan_kernel",
                 "polar_generate": "polar_gen_kernel<float, MODE_BATCHED>",
                 "b1_batched": "b1_batched_kernel<float>",
@@ -83,7 +88,8 @@ KERNEL_NAMES = {"polar_count": "polar_mask_kernel<MODE_BATCHED> + polar_scan_ker
                 "p2_generate": "polar_gen_kernel<float, MODE_BATCHED, VM_P2>",
                 "b3_batched": "b1_batched_kernel<float, BM_B3>",
                 "ratio_count": "polar_mask_kernel<MODE_BATCHED, VM_R> + polar_scan_kernel",
-                "ratio_generate": "polar_gen_kernel<float, MODE_BATCHED, VM_R>"}
+                "ratio_generate": "polar_gen_kernel<float, MODE_BATCHED, VM_R>",
+                "b2_batched": "b1_batched_kernel<float, BM_B2>"}
 PROFILES = os.path.join(ROOT, "profiles")
 
 
@@ -132,10 +138,10 @@ def main() -> int:
     ap.add_argument("--nstreams", type=int, default=4096)
     ap.add_argument("--no-extras", action="store_true", help="skip the side measurements")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--only", choices=["b1", "polar", "p2", "b3", "ratio"], default=None,
-                    help="time one method only (for profiling runs; p2, b3 and ratio = method P2 of Section 4, "
-                         "method B3 of Section 3 and Algorithm R of Section 5, which are otherwise measured "
-                         "among the extras)")
+    ap.add_argument("--only", choices=["b1", "polar", "p2", "b3", "ratio", "b2"], default=None,
+                    help="time one method only (for profiling runs; p2, b3, ratio and b2 = method P2 of "
+                         "Section 4, methods B3 and B2 of Section 3 and Algorithm R of Section 5, which are "
+                         "otherwise measured among the extras)")
     ap.add_argument("--calibrate", action="store_true",
                     help="also run a 1 GiB copy and a 1 GiB store probe once (known traffic, for scaling "
                          "hardware byte counters in profiling runs)")
@@ -173,7 +179,8 @@ def main() -> int:
         "sigma": torch.from_numpy(cfg["sigma"]).to(dev),
     }
     methods = [("b1", nb.NRNG_METHOD_B1), ("polar", nb.NRNG_METHOD_POLAR)]
-    extra_methods = {"p2": nb.NRNG_METHOD_P2, "b3": nb.NRNG_METHOD_B3, "ratio": nb.NRNG_METHOD_R}
+    extra_methods = {"p2": nb.NRNG_METHOD_P2, "b3": nb.NRNG_METHOD_B3, "ratio": nb.NRNG_METHOD_R,
+                     "b2": nb.NRNG_METHOD_B2}
     if args.only in extra_methods:
         methods = [(args.only, extra_methods[args.only])]
     elif args.only:
@@ -295,10 +302,10 @@ def main() -> int:
 
 
 def extra_batched(nb, torch, stream, D, ns, total, pairs, steps, per_kernel, m):
-    """Method P2 (Section 4), B3 (Section 3) or Algorithm R (Section 5) on the
+    """Method P2 (Section 4), B3 or B2 (Section 3) or Algorithm R (Section 5) on the
     same batched workload, timed like the step's legs: plan, then exec part 1
-    (P2, R: the mask and scan kernels; B3: nothing) and part 2 (the generate
-    kernel; the B3 kernel) between events."""
+    (P2, R: the mask and scan kernels; B3, B2: nothing) and part 2 (the
+    generate kernel; the B3 or B2 kernel) between events."""
     out = torch.empty(total, dtype=torch.float32, device=D["n"].device)
     cons = torch.zeros(ns, dtype=torch.int64, device=D["n"].device)
 
@@ -340,11 +347,12 @@ def extra_batched(nb, torch, stream, D, ns, total, pairs, steps, per_kernel, m):
                  "ratio_generate": (gen_ms, ALU_OPS["ratio_generate"] * total)}
     else:
         r["consumed_uniforms"] = int(u64sum(cons))
-        units = {"b3_batched": (gen_ms, ALU_OPS["b3_batched"] * pairs)}
+        key = "b3_batched" if m == nb.NRNG_METHOD_B3 else "b2_batched"
+        units = {key: (gen_ms, ALU_OPS[key] * pairs)}
     for k, (ms, ops) in units.items():
         r["alu"][k] = {"ms": round(ms, 5), "Tops_per_s": round(ops / (ms * 1e-3) / 1e12, 2),
                        "frac_valu_peak": round(ops / (ms * 1e-3) / 1e12 / VALU_PEAK_TOPS, 4)}
-    ref = "b1" if m == nb.NRNG_METHOD_B3 else "polar"
+    ref = "b1" if m in (nb.NRNG_METHOD_B3, nb.NRNG_METHOD_B2) else "polar"
     if ref in per_kernel:
         r["exec_vs_" + ref] = round(per_kernel[ref]["exec_ms"] / exec_ms, 4)
     return r
@@ -398,6 +406,8 @@ def extras(nb, torch, dev, stream, per_kernel, batched_value):
         r["b3_normals_per_s"] = n / (ms * 1e-3)
         ms = timed(lambda: nb.nrng_ratio(21, 0, n, 0.0, 1.0, out, dt, stream, None), 3)
         r["ratio_normals_per_s"] = n / (ms * 1e-3)
+        ms = timed(lambda: nb.nrng_b2(1, 0, n, 0.0, 1.0, out, dt, stream), 5)
+        r["b2_normals_per_s"] = n / (ms * 1e-3)
         single[name] = r
         del out
         torch.cuda.empty_cache()
@@ -450,7 +460,7 @@ def cpu_baseline(cfg, methods):
 
     def work(mj):
         m, j = mj
-        fn = {"b1": O.b1, "polar": O.polar, "p2": O.polar2, "b3": O.b3, "ratio": O.ratio}[m]
+        fn = {"b1": O.b1, "polar": O.polar, "p2": O.polar2, "b3": O.b3, "ratio": O.ratio, "b2": O.b2}[m]
         fn(int(cfg["seed"][j]), int(cfg["offset"][j]), int(cfg["n"][j]), float(cfg["mu"][j]), float(cfg["sigma"][j]))
         return int(cfg["n"][j])
 

@@ -5,8 +5,8 @@
  * The library turns a counter-based stream of uniform deviates into
  * N(mu, sigma^2) deviates by the two methods of Section 2 of R. P. Brent,
  * "Fast Normal Random Number Generators for Vector Processors" (1993), and
- * by the paper's methods B3 (Section 3, see nrng_b3), P2 (Section 4, see
- * nrng_polar2) and Algorithm R (Section 5, see nrng_ratio):
+ * by the paper's methods B2 and B3 (Section 3, see nrng_b2 and nrng_b3), P2
+ * (Section 4, see nrng_polar2) and Algorithm R (Section 5, see nrng_ratio):
  *
  *   Algorithm B1 (Box-Muller):  r = sigma sqrt(-2 ln(1 - u)),
  *                               x = r sin(2 pi v) + mu,  y = r cos(2 pi v) + mu;
@@ -74,7 +74,8 @@ enum nrng_method {
     NRNG_METHOD_POLAR = 1,
     NRNG_METHOD_P2 = 2,
     NRNG_METHOD_B3 = 3,
-    NRNG_METHOD_R = 4
+    NRNG_METHOD_R = 4,
+    NRNG_METHOD_B2 = 5
 };
 
 /* Status codes. */
@@ -131,6 +132,25 @@ int nrng_boxmuller(uint64_t seed, uint64_t offset, uint64_t n, double mu, double
  * Consumes exactly 3 ceil(n/2) uniforms.  Arguments, errors and launch
  * configuration (nrng_tune_set kernel 0) as nrng_boxmuller. */
 int nrng_b3(uint64_t seed, uint64_t offset, uint64_t n, double mu, double sigma, void *out, int dtype,
+            void *stream);
+
+/* ------------------------------------------------------------------------
+ * Method B2 (Section 3), over one stream: B1 with the sine and cosine
+ * computed inline.  Pair k uses the u and v of B1's pair k:
+ *   r = sigma sqrt(-2 ln(1 - u));  y = (2 pi v - pi)/16 (|y| <= pi/16);
+ *   sin y ~= s1 y + s3 y^3 + s5 y^5 + s7 y^7, cos y ~= c0 + c2 y^2 + c4 y^4 +
+ *   c6 y^6 (the Chebyshev series of sin(y)/y and cos y in y^2 on
+ *   [0, (pi/16)^2], truncated after T_3), then four doublings
+ *   sin 2y = 2 sin y cos y, cos 2y = 1 - 2 sin^2 y;
+ *   output 2k = r sin(16y) + mu, output 2k+1 = r cos(16y) + mu.
+ * Since 16y = 2 pi v - pi, pair k equals B1's pair k negated about mu, up to
+ * the approximation (absolute error below 2e-12 r in FP64).  The FP64 kernel
+ * keeps the method's order of operations; the FP32 kernel reduces the angle
+ * to a quarter turn first and its sine and cosine are accurate to about
+ * 2^-20 absolute.  Consumes exactly 2 ceil(n/2) uniforms.  Arguments,
+ * errors and launch configuration (nrng_tune_set kernel 0) as
+ * nrng_boxmuller. */
+int nrng_b2(uint64_t seed, uint64_t offset, uint64_t n, double mu, double sigma, void *out, int dtype,
             void *stream);
 
 /* ------------------------------------------------------------------------
@@ -203,7 +223,8 @@ int nrng_polar_dev(uint64_t seed, uint64_t *d_cursor, uint64_t n, double mu, dou
  * Many independent streams in one launch sequence: one small set-up kernel
  * builds the tile table on the device, then one persistent B1 kernel, or
  * the three Polar kernels, cover every stream.
- *   method       NRNG_METHOD_B1, NRNG_METHOD_POLAR, NRNG_METHOD_P2, NRNG_METHOD_B3 or NRNG_METHOD_R
+ *   method       NRNG_METHOD_B1, NRNG_METHOD_POLAR, NRNG_METHOD_P2, NRNG_METHOD_B3, NRNG_METHOD_R or
+ *                NRNG_METHOD_B2
  *   nstreams     number of streams (0 is a no-op)
  *   d_seed[j], d_offset[j], d_n[j]  stream j's seed, first counter, length
  *   d_out_off[j] element offset of stream j's output in `out`; NULL means
@@ -213,7 +234,8 @@ int nrng_polar_dev(uint64_t seed, uint64_t *d_cursor, uint64_t n, double mu, dou
  *                range [out_off, out_off + n) does not fit are skipped
  *   d_consumed   optional (may be NULL): d_consumed[j] receives stream j's
  *                consumed uniforms, or UINT64_MAX if the stream was skipped.
- * Stream j's values equal those of nrng_boxmuller / nrng_polar / nrng_polar2 / nrng_b3 / nrng_ratio called alone
+ * Stream j's values equal those of nrng_boxmuller / nrng_polar / nrng_polar2 / nrng_b3 / nrng_ratio / nrng_b2
+ * called alone
  * with (d_seed[j], d_offset[j], d_n[j], d_mu[j], d_sigma[j]), bit for bit.
  * The total of d_n over valid streams must not exceed out_len; otherwise the
  * device-side check fails the whole call (every d_consumed[j] = UINT64_MAX,
@@ -282,6 +304,7 @@ int nrng_tune_variants(int kernel, uint32_t *pairs, int max_pairs);
  *   d_words[2p+1] (64-bit hash words); writes out[2p], out[2p+1].
  * nrng_test_b3_words: the same for method B3, three words per pair (u1,
  *   u2, u3), d_words holding 3 npairs words.
+ * nrng_test_b2_words: the same as nrng_test_b1_words for method B2.
  * nrng_test_polar_xy: candidate j is (d_xy[2j], d_xy[2j+1]); accepted
  *   candidates are written compactly in order to out (capacity 2 ncand);
  *   d_mask_words (ceil(ncand/64) words, bit j%64 of word j/64 = accept) and
@@ -305,6 +328,8 @@ int nrng_tune_variants(int kernel, uint32_t *pairs, int max_pairs);
 int nrng_test_b1_words(const uint64_t *d_words, uint64_t npairs, double mu, double sigma, void *out, int dtype,
                        void *stream);
 int nrng_test_b3_words(const uint64_t *d_words, uint64_t npairs, double mu, double sigma, void *out, int dtype,
+                       void *stream);
+int nrng_test_b2_words(const uint64_t *d_words, uint64_t npairs, double mu, double sigma, void *out, int dtype,
                        void *stream);
 int nrng_test_polar_xy(const int32_t *d_xy, uint64_t ncand, double mu, double sigma, void *out, int dtype,
                        uint64_t *d_mask_words, uint64_t *d_count, void *stream);

@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libnrng.so")
 
 NRNG_F64, NRNG_F32, NRNG_BF16, NRNG_F16 = 0, 1, 2, 3
-NRNG_METHOD_B1, NRNG_METHOD_POLAR, NRNG_METHOD_P2, NRNG_METHOD_B3, NRNG_METHOD_R = 0, 1, 2, 3, 4
+NRNG_METHOD_B1, NRNG_METHOD_POLAR, NRNG_METHOD_P2, NRNG_METHOD_B3, NRNG_METHOD_R, NRNG_METHOD_B2 = 0, 1, 2, 3, 4, 5
 NRNG_OK, NRNG_EINVAL, NRNG_EDTYPE, NRNG_ERANGE = 0, -1, -2, -3
 NRNG_EHIP, NRNG_ENODEV, NRNG_ECAPTURE, NRNG_ENOMEM = -4, -5, -6, -7
 KERNEL_B1, KERNEL_POLAR, KERNEL_B1_BATCHED = 0, 1, 2
@@ -33,6 +33,7 @@ _SIGS = {
     "nrng_reserve": (_i32, [_u64, _u32]),
     "nrng_boxmuller": (_i32, [_u64, _u64, _u64, _f64, _f64, _vp, _i32, _vp]),
     "nrng_b3": (_i32, [_u64, _u64, _u64, _f64, _f64, _vp, _i32, _vp]),
+    "nrng_b2": (_i32, [_u64, _u64, _u64, _f64, _f64, _vp, _i32, _vp]),
     "nrng_polar": (_i32, [_u64, _u64, _u64, _f64, _f64, _vp, _i32, _vp, _vp]),
     "nrng_polar2": (_i32, [_u64, _u64, _u64, _f64, _f64, _vp, _i32, _vp, _vp]),
     "nrng_ratio": (_i32, [_u64, _u64, _u64, _f64, _f64, _vp, _i32, _vp, _vp]),
@@ -49,6 +50,7 @@ _SIGS = {
     "nrng_tune_variants": (_i32, [_i32, ctypes.POINTER(_u32), _i32]),
     "nrng_test_b1_words": (_i32, [_vp, _u64, _f64, _f64, _vp, _i32, _vp]),
     "nrng_test_b3_words": (_i32, [_vp, _u64, _f64, _f64, _vp, _i32, _vp]),
+    "nrng_test_b2_words": (_i32, [_vp, _u64, _f64, _f64, _vp, _i32, _vp]),
     "nrng_test_polar_xy": (_i32, [_vp, _u64, _f64, _f64, _vp, _i32, _vp, _vp, _vp]),
     "nrng_test_polar2_xy": (_i32, [_vp, _u64, _f64, _f64, _vp, _i32, _vp, _vp, _vp]),
     "nrng_test_ratio_words": (_i32, [_vp, _u64, _f64, _f64, _vp, _i32, _vp, _vp, _vp]),
@@ -158,6 +160,12 @@ def nrng_boxmuller(seed, offset, n, mu, sigma, out, dtype, stream=None) -> None:
 def nrng_b3(seed, offset, n, mu, sigma, out, dtype, stream=None) -> None:
     _need(out, n * _ESIZE.get(dtype, 0), "nrng_b3 out")
     _check("nrng_b3", lib().nrng_b3(seed & (2**64 - 1), offset & (2**64 - 1), n, mu, sigma, _ptr(out), dtype,
+                                    _stream(stream)))
+
+
+def nrng_b2(seed, offset, n, mu, sigma, out, dtype, stream=None) -> None:
+    _need(out, n * _ESIZE.get(dtype, 0), "nrng_b2 out")
+    _check("nrng_b2", lib().nrng_b2(seed & (2**64 - 1), offset & (2**64 - 1), n, mu, sigma, _ptr(out), dtype,
                                     _stream(stream)))
 
 
@@ -275,6 +283,13 @@ def nrng_test_b3_words(d_words, npairs, mu, sigma, out, dtype, stream=None) -> N
     _need(d_words, 24 * npairs, "nrng_test_b3_words d_words")
     _need(out, 2 * npairs * _ESIZE.get(dtype, 0), "nrng_test_b3_words out")
     _check("nrng_test_b3_words", lib().nrng_test_b3_words(_ptr(d_words), npairs, mu, sigma, _ptr(out), dtype,
+                                                          _stream(stream)))
+
+
+def nrng_test_b2_words(d_words, npairs, mu, sigma, out, dtype, stream=None) -> None:
+    _need(d_words, 16 * npairs, "nrng_test_b2_words d_words")
+    _need(out, 2 * npairs * _ESIZE.get(dtype, 0), "nrng_test_b2_words out")
+    _check("nrng_test_b2_words", lib().nrng_test_b2_words(_ptr(d_words), npairs, mu, sigma, _ptr(out), dtype,
                                                           _stream(stream)))
 
 

@@ -36,7 +36,7 @@ struct DevState {
     uint64_t stream_cap = 0;
     int occ_polar[3][4][4][8] = {};  // generate kernel: [value method][mode][dtype][variant], 0 = not queried
     int occ_mask[3][4][8] = {};      // mask kernel: [value method][mode][variant]
-    int occ_b1[2][2][4][8] = {};     // [B1 / B3][batched][dtype][variant]
+    int occ_b1[3][2][4][8] = {};     // [B1 / B3 / B2][batched][dtype][variant]
     // the tile table currently in the workspace (from nrng_batched_plan)
     int plan_method = -1, plan_dtype = -1, plan_vi = -1;
     uint32_t plan_nstreams = 0;
@@ -273,16 +273,21 @@ PolarArgs polar_args(DevState &d)
 int method_vm(int method) { return method == NRNG_METHOD_P2 ? 1 : (method == NRNG_METHOD_R ? 2 : 0); }
 int vm_method(int vm) { return vm == 1 ? NRNG_METHOD_P2 : (vm == 2 ? NRNG_METHOD_R : NRNG_METHOD_POLAR); }
 
-// Box-Muller family (B1, B3): one kernel per tile of pairs, no compaction.
-bool method_bm(int method) { return method == NRNG_METHOD_B1 || method == NRNG_METHOD_B3; }
+// Box-Muller family (B1, B3, B2): one kernel per tile of pairs, no
+// compaction.  Kernel family member: 0 = B1, 1 = B3, 2 = B2.
+bool method_bm(int method)
+{
+    return method == NRNG_METHOD_B1 || method == NRNG_METHOD_B3 || method == NRNG_METHOD_B2;
+}
+int bm_of_method(int method) { return method == NRNG_METHOD_B3 ? 1 : (method == NRNG_METHOD_B2 ? 2 : 0); }
 
 bool method_ok(int method)
 {
     return method == NRNG_METHOD_B1 || method == NRNG_METHOD_POLAR || method == NRNG_METHOD_P2 ||
-           method == NRNG_METHOD_B3 || method == NRNG_METHOD_R;
+           method == NRNG_METHOD_B3 || method == NRNG_METHOD_R || method == NRNG_METHOD_B2;
 }
 
-// B1 (bm 0) or B3 (bm 1) over one stream.
+// B1 (bm 0), B3 (bm 1) or B2 (bm 2) over one stream.
 int bm_single(int bm, uint64_t seed, uint64_t offset, uint64_t n, double mu, double sigma, void *out, int dtype,
               hipStream_t s)
 {
@@ -508,6 +513,11 @@ int nrng_b3(uint64_t seed, uint64_t offset, uint64_t n, double mu, double sigma,
     return bm_single(1, seed, offset, n, mu, sigma, out, dtype, S(stream));
 }
 
+int nrng_b2(uint64_t seed, uint64_t offset, uint64_t n, double mu, double sigma, void *out, int dtype, void *stream)
+{
+    return bm_single(2, seed, offset, n, mu, sigma, out, dtype, S(stream));
+}
+
 int nrng_polar(uint64_t seed, uint64_t offset, uint64_t n, double mu, double sigma, void *out, int dtype,
                void *stream, uint64_t *d_consumed)
 {
@@ -664,8 +674,8 @@ int nrng_batched_exec_part(int part, int method, uint32_t nstreams, const uint64
         a.mus = d_mu;
         a.sigmas = d_sigma;
         if (part == 1)
-            return NRNG_OK;   // B1 and B3 have no count pass
-        const int bm = method == NRNG_METHOD_B3 ? 1 : 0;
+            return NRNG_OK;   // the Box-Muller family has no count pass
+        const int bm = bm_of_method(method);
         const uint32_t grid = persistent_grid(*d, b1_blocks_per_cu(*d, 1, bm, dtype, tu.vi), tu.grid_per_cu, 0);
         return hip_status(launch_b1_batched(bm, dtype, tu.vi, a, grid, s));
     }
@@ -839,6 +849,12 @@ int nrng_test_b3_words(const uint64_t *d_words, uint64_t npairs, double mu, doub
                        void *stream)
 {
     return bm_words(1, d_words, npairs, mu, sigma, out, dtype, S(stream));
+}
+
+int nrng_test_b2_words(const uint64_t *d_words, uint64_t npairs, double mu, double sigma, void *out, int dtype,
+                       void *stream)
+{
+    return bm_words(2, d_words, npairs, mu, sigma, out, dtype, S(stream));
 }
 
 int nrng_test_polar_xy(const int32_t *d_xy, uint64_t ncand, double mu, double sigma, void *out, int dtype,

@@ -10,6 +10,7 @@
 #include <stdint.h>
 
 #include "nrng_launch.hpp"
+#include "nrng_b2_poly.hpp"
 #include "nrng_p2_poly.hpp"
 
 namespace nrng {
@@ -202,8 +203,7 @@ __device__ __forceinline__ void b1_pair_f64(uint64_t ku, uint64_t kv, double mu,
 //    angle has absolute error at most 2^-27 turns.  v_sin_f32 / v_cos_f32
 //    take revolutions.
 //  * sigma is folded in as r = sqrt(log2(1 - u) * (-2 ln 2 sigma^2)).
-__device__ __forceinline__ void b1_pair_f32(uint64_t ku, uint32_t kv_hi, float mu, float k2, float& x,
-                                            float& y)
+__device__ __forceinline__ float bm_radius_f32(uint64_t ku, float k2)
 {
     const uint64_t t = ku & ~0x7FFull;
     const bool lowhalf = t < 0x8000000000000000ull;
@@ -214,8 +214,13 @@ __device__ __forceinline__ void b1_pair_f32(uint64_t ku, uint32_t kv_hi, float m
     const float corr = lowhalf ? d * (2.0f - yv) : 0.0f;
     const float arg = lowhalf ? yv : qf;
     const float l2 = __builtin_fmaf(corr, 1.4426950408889634f, __builtin_amdgcn_logf(arg));  // log2(1 - u)
-    float r = __builtin_amdgcn_sqrtf(l2 * k2);
+    return __builtin_amdgcn_sqrtf(l2 * k2);
+}
 
+__device__ __forceinline__ void b1_pair_f32(uint64_t ku, uint32_t kv_hi, float mu, float k2, float& x,
+                                            float& y)
+{
+    float r = bm_radius_f32(ku, k2);
     // a / 2^32 = v - round(v); flip when a lies outside [-2^30, 2^30)
     const bool flip = (kv_hi + 0x40000000u) >= 0x80000000u;
     const int32_t a = (int32_t)(flip ? (kv_hi ^ 0x80000000u) : kv_hi);
@@ -225,6 +230,71 @@ __device__ __forceinline__ void b1_pair_f32(uint64_t ku, uint32_t kv_hi, float m
     const float cs = __builtin_amdgcn_cosf(turns);
     x = __builtin_fmaf(r, sn, mu);
     y = __builtin_fmaf(r, cs, mu);
+}
+
+// ---------------------------------------------------------------------------
+// Method B2 (Section 3): B1 with the sine and cosine of the angle 2 pi v - pi
+// computed inline: with y = (2 pi v - pi)/16, sin y and cos y from the odd
+// and even polynomials of nrng_b2_poly.hpp (t = y^2, nested form), then four
+// doublings sin 2y = 2 sin y cos y, cos 2y = 1 - 2 sin^2 y.  Outputs
+// r sin(16 y) + mu, then r cos(16 y) + mu.
+// ---------------------------------------------------------------------------
+
+// FP64: the order of the method with one rounding per operation, as in
+// b1_pair_f64; the radius is B1's.
+__device__ __forceinline__ void b2_pair_f64(uint64_t ku, uint64_t kv, double mu, double sigma, double& x,
+                                            double& y)
+{
+#pragma clang fp contract(off)
+    const double pi = 3.141592653589793115997963;
+    double u = (double)(ku >> 11) * 0x1p-53;
+    double v = (double)(kv >> 11) * 0x1p-53;
+    double r = sigma * sqrt(-2.0 * log(1.0 - u));
+    double yy = ((2.0 * pi) * v - pi) / 16.0;
+    double t = yy * yy;
+    double s = yy * (kB2SinF64[0] + t * (kB2SinF64[1] + t * (kB2SinF64[2] + t * kB2SinF64[3])));
+    double c = kB2CosF64[0] + t * (kB2CosF64[1] + t * (kB2CosF64[2] + t * kB2CosF64[3]));
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        double s2 = 2.0 * s * c;
+        c = 1.0 - 2.0 * s * s;
+        s = s2;
+    }
+    x = r * s + mu;
+    y = r * c + mu;
+}
+
+// FP32.  The angle 2 pi v - pi is B1's angle minus half a turn, so B2's pair
+// is B1's with r negated; B1's reduction to a quarter turn (the signed
+// fraction a 2^-32 of a turn, |a| <= 2^30, half a turn added and r negated
+// beyond) is reused, so y = 2 pi a 2^-32 / 16 has |y| <= pi/32 and
+// 16 y = 2 pi a 2^-32.  Polynomials by FMA; each doubling forms d = 2s
+// (exact), s' = d c and c' = 1 - d s with one rounding (FMA).  The absolute
+// error of sin 16y and cos 16y is below about 2^-20 (the doublings'
+// cancellation in 1 - 2 sin^2 near cos = 0), against about 2^-22 for the
+// hardware sine and cosine of B1.
+__device__ __forceinline__ void b2_pair_f32(uint64_t ku, uint32_t kv_hi, float mu, float k2, float& x,
+                                            float& y)
+{
+    float r = bm_radius_f32(ku, k2);
+    const bool flip = (kv_hi + 0x40000000u) >= 0x80000000u;
+    const int32_t a = (int32_t)(flip ? (kv_hi ^ 0x80000000u) : kv_hi);
+    r = flip ? r : -r;
+    const float yy = cvt_f32_i32(a) * 0x1.921fb6p-34f;          // 2 pi 2^-32 / 16 = pi 2^-35
+    const float t = yy * yy;
+    float s = yy * __builtin_fmaf(t, __builtin_fmaf(t, __builtin_fmaf(t, kB2SinF32[3], kB2SinF32[2]), kB2SinF32[1]),
+                                  kB2SinF32[0]);
+    float c = __builtin_fmaf(t, __builtin_fmaf(t, __builtin_fmaf(t, kB2CosF32[3], kB2CosF32[2]), kB2CosF32[1]),
+                             kB2CosF32[0]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const float d = s + s;
+        const float cn = __builtin_fmaf(-d, s, 1.0f);
+        s = d * c;
+        c = cn;
+    }
+    x = __builtin_fmaf(r, s, mu);
+    y = __builtin_fmaf(r, c, mu);
 }
 
 // ---------------------------------------------------------------------------

@@ -131,6 +131,28 @@ def b3_edge_words(seed: int = 15) -> np.ndarray:
     return np.concatenate([arr, rnd])
 
 
+def b2_edge_words(seed: int = 17) -> np.ndarray:
+    """Explicit 64-bit hash words for the B2 test hook, as (u-word, v-word)
+    pairs: v at every sixteenth of a turn and one unit (of 2^-53, and of the
+    top 32 bits) beside it, v across the quarter-turn boundaries of the FP32
+    angle reduction, u = 0, 1/2 and 1 - 2^-53 (the largest radius), and
+    random words."""
+    g = rng(seed)
+    T = 1 << 11                       # one unit of a 53-bit uniform
+    H = 1 << 32                       # one unit of the top 32 bits
+    top = (1 << 64) - T
+    us = [0, 1 << 63, top, top - T, 3 << 62]
+    vs = []
+    for k in range(16):
+        base = k << 60
+        vs += [(base + d) % (1 << 64) for d in (0, T, -T, H, -H)]
+    for b in (1 << 62, 3 << 62):      # quarter-turn boundaries of v - 1/2
+        vs += [(b + d) % (1 << 64) for d in (0, T, -T, H, -H, 2 * H, -2 * H)]
+    pairs = [(u, v) for u in us for v in vs]
+    rv = g.integers(0, 2**64, 2 * 8192, dtype=np.uint64, endpoint=False)
+    return np.concatenate([np.array(pairs, dtype=np.uint64).reshape(-1), rv])
+
+
 def ratio_edge_words(seed: int = 16) -> np.ndarray:
     """Explicit 64-bit hash words for the Algorithm R test hook, two per
     candidate (u-word, v-word; u = (w >> 11) 2^-53): u = 0 with several v;

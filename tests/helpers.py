@@ -89,6 +89,18 @@ def fp64_poly_tol(z_ref: np.ndarray, mu, sigma) -> np.ndarray:
     return fp64_scaled_tol(z, mu, sigma) + 4e-15 * np.abs(z - mu)
 
 
+def b2_f32_extra(ref_pairs: np.ndarray, mu, n: int) -> np.ndarray:
+    """Extra absolute FP32 tolerance of method B2: after four angle doublings
+    in single precision the sine and cosine carry an absolute error of up to
+    about 2^-20 (1 - 2 sin^2 cancels near cos = 0; 8.4 2^-24 measured over
+    1.7e7 angles, about 24 2^-24 by a rounding-error bound), so each value may
+    be off by that times sigma r, r the pair's radius.  ref_pairs holds the
+    oracle's complete pairs (even length); the result is cut to n values."""
+    d = (np.asarray(ref_pairs, dtype=np.float64) - mu).reshape(-1, 2)
+    sr = np.hypot(d[:, 0], d[:, 1])
+    return np.repeat(2.0**-19 * sr, 2)[:n]
+
+
 def ulp_of(x: np.ndarray, dtype) -> np.ndarray:
     """Spacing of the target format at |x| (normal and subnormal range)."""
     x = np.abs(np.asarray(x, dtype=np.float64))

@@ -62,7 +62,7 @@ def test_argument_errors_return_before_any_launch():
     assert L.nrng_boxmuller(1, 0, 0, 0.0, 1.0, None, 1, None) == nb.NRNG_OK
     assert L.nrng_polar(1, 0, 0, 0.0, 1.0, None, 1, None, None) == nb.NRNG_OK
     # batched: bad method, zero streams, null arrays
-    assert L.nrng_batched(5, 4, p, p, p, None, p, p, p, 100, 1, None, None) == nb.NRNG_EINVAL
+    assert L.nrng_batched(6, 4, p, p, p, None, p, p, p, 100, 1, None, None) == nb.NRNG_EINVAL
     assert L.nrng_batched(0, 0, None, None, None, None, None, None, None, 0, 1, None, None) == nb.NRNG_OK
     assert L.nrng_batched(1, 4, None, p, p, None, p, p, p, 100, 1, None, None) == nb.NRNG_EINVAL
     assert L.nrng_batched(1, 4, p, p, p, None, p, p, None, 100, 1, None, None) == nb.NRNG_EINVAL
@@ -106,3 +106,37 @@ def test_binding_checks_tensor_sizes_before_calling():
         nb.nrng_batched(nb.NRNG_METHOD_POLAR, 2, None, None, None, None, None, None, small, 11, nb.NRNG_F32, 0)
     with pytest.raises(ValueError):
         nb.nrng_test_polar_xy(torch.empty(3, dtype=torch.int32), 2, 0.0, 1.0, small, nb.NRNG_F32, None, None, 0)
+
+
+def test_b2_kernel_coefficients_equal_the_oracles():
+    """Method B2's coefficients are derived twice, independently: by the
+    kernels' generator (mpmath quadrature of the Chebyshev coefficients,
+    csrc/gen_b2_poly.py) and by the oracle (the truncated series from the
+    Taylor series, in long double).  Both round the same truncated series to
+    double, so the FP64 values must agree bit for bit; the FP32 ones are
+    those doubles rounded to single precision."""
+    import numpy as np
+    import oracle as O
+    text = open(os.path.join(ROOT, "paper_1004_3105_amd", "csrc", "nrng_b2_poly.hpp")).read()
+
+    def arr(name):
+        body = re.search(name + r"\[4\] = \{([^}]*)\}", text).group(1)
+        return [float.fromhex(x.strip().rstrip("f")) for x in body.split(",")]
+
+    s, c = O.b2_coef()
+    assert arr("kB2SinF64") == list(s)
+    assert arr("kB2CosF64") == list(c)
+    assert arr("kB2SinF32") == [float(np.float32(x)) for x in s]
+    assert arr("kB2CosF32") == [float(np.float32(x)) for x in c]
+
+
+def test_b2_argument_errors():
+    L = nb.lib()
+    p = ctypes.c_void_p(0x1000)
+    assert L.nrng_b2(1, 0, 10, 0.0, 1.0, p, 7, None) == nb.NRNG_EDTYPE
+    assert L.nrng_b2(1, 0, 10, 0.0, -1.0, p, 1, None) == nb.NRNG_EINVAL
+    assert L.nrng_b2(1, 0, 10, 0.0, 1.0, None, 1, None) == nb.NRNG_EINVAL
+    assert L.nrng_b2(1, 0, 0, 0.0, 1.0, None, 1, None) == nb.NRNG_OK
+    assert L.nrng_test_b2_words(None, 4, 0.0, 1.0, p, 1, None) == nb.NRNG_EINVAL
+    assert L.nrng_batched(nb.NRNG_METHOD_B2, 4, p, p, p, None, p, p, p, 100, 9, None, None) == nb.NRNG_EDTYPE
+    assert L.nrng_batched(6, 4, p, p, p, None, p, p, p, 100, 1, None, None) == nb.NRNG_EINVAL

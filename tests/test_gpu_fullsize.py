@@ -24,7 +24,7 @@ import torch
 import oracle as O
 import synth
 from gpu_util import assert_close, case, dev, host, u64
-from helpers import stat_bounds
+from helpers import b2_f32_extra, stat_bounds
 from paper_1004_3105_amd import binding as nb
 
 pytestmark = pytest.mark.gpu
@@ -103,7 +103,7 @@ def test_polar_single_stream_2e30_sampled():
 
 
 @pytest.mark.parametrize("method", [nb.NRNG_METHOD_B1, nb.NRNG_METHOD_POLAR, nb.NRNG_METHOD_P2, nb.NRNG_METHOD_B3,
-                                    nb.NRNG_METHOD_R])
+                                    nb.NRNG_METHOD_R, nb.NRNG_METHOD_B2])
 def test_batched_full_workload_sampled(method):
     d = dev()
     cfg = synth.batched_streams()
@@ -119,7 +119,7 @@ def test_batched_full_workload_sampled(method):
     torch.cuda.synchronize()
     c = u64(cons)
     n = cfg["n"].astype(np.int64)
-    if method == nb.NRNG_METHOD_B1:
+    if method in (nb.NRNG_METHOD_B1, nb.NRNG_METHOD_B2):
         assert np.array_equal(c, (2 * ((n + 1) // 2)).astype(np.uint64))
     if method == nb.NRNG_METHOD_B3:
         assert np.array_equal(c, (3 * ((n + 1) // 2)).astype(np.uint64))
@@ -127,13 +127,18 @@ def test_batched_full_workload_sampled(method):
     pick = sorted({int(order[0]), int(order[-1]), int(order[ns // 2])} |
                   set(synth.rng(33).integers(0, ns, 24).tolist()))
     fn = {nb.NRNG_METHOD_B1: O.b1, nb.NRNG_METHOD_POLAR: O.polar, nb.NRNG_METHOD_P2: O.polar2,
-          nb.NRNG_METHOD_B3: O.b3, nb.NRNG_METHOD_R: O.ratio}[method]
+          nb.NRNG_METHOD_B3: O.b3, nb.NRNG_METHOD_R: O.ratio, nb.NRNG_METHOD_B2: O.b2}[method]
     for j in pick:
         o0 = int(cfg["out_off"][j])
-        ref, used = fn(int(cfg["seed"][j]), 0, int(n[j]), float(cfg["mu"][j]), float(cfg["sigma"][j]))
+        mu, sg = float(cfg["mu"][j]), float(cfg["sigma"][j])
+        ref, used = fn(int(cfg["seed"][j]), 0, int(n[j]), mu, sg)
         assert int(c[j]) == used, j
-        assert_close(host(out[o0:o0 + int(n[j])]), ref, nb.NRNG_F32, float(cfg["mu"][j]), float(cfg["sigma"][j]),
-                     what="batched stream %d" % j)
+        extra = None
+        if method == nb.NRNG_METHOD_B2:
+            pairs, _ = O.b2(int(cfg["seed"][j]), 0, 2 * ((int(n[j]) + 1) // 2), mu, sg)
+            extra = b2_f32_extra(pairs, mu, int(n[j]))
+        assert_close(host(out[o0:o0 + int(n[j])]), ref, nb.NRNG_F32, mu, sg, what="batched stream %d" % j,
+                     extra=extra)
     if method in (nb.NRNG_METHOD_POLAR, nb.NRNG_METHOD_P2, nb.NRNG_METHOD_R):
         # every stream's consumed count: at least the minimum 2 ceil(n/2),
         # even, and (for the sampled streams above) exactly the oracle's
