@@ -99,7 +99,7 @@ def u64sum(t) -> int:
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("nrng_kernels.hip", "nrng_device.hpp", "nrng_p2_poly.hpp"):
+    for f in ("nrng_kernels.hip", "nrng_device.hpp", "nrng_p2_poly.hpp", "nrng_b2_poly.hpp"):
         with open(os.path.join(ROOT, "paper_1004_3105_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
