@@ -171,6 +171,22 @@ def b1_at(seed: int, offset: int, index: np.ndarray, mu: float = 0.0, sigma: flo
     return out
 
 
+def pairs_at(method: str, seed: int, offset: int, index: np.ndarray, mu: float = 0.0,
+             sigma: float = 1.0) -> np.ndarray:
+    """Values at the given output indices of a stream of a Box-Muller-family
+    method ("b1", "b2" or "b3"; pair k uses uniforms upp k .. upp k + upp - 1,
+    upp = 2, 2, 3), each index computed on its own from its pair."""
+    index = np.asarray(index, dtype=np.int64)
+    out = np.empty(index.size, dtype=np.float64)
+    pair = np.empty(2, dtype=np.float64)
+    L = lib()
+    fn, upp = {"b1": (L.orc_b1, 2), "b2": (L.orc_b2, 2), "b3": (L.orc_b3, 3)}[method]
+    for t, k in enumerate(index.tolist()):
+        fn(seed & M64, (offset + upp * (k // 2)) & M64, 2, mu, sigma, _p(pair))
+        out[t] = pair[k % 2]
+    return out
+
+
 def b1_parallel(seed: int, offset: int, n: int, mu: float = 0.0, sigma: float = 1.0,
                 threads: int | None = None, chunk_pairs: int = 1 << 20) -> np.ndarray:
     """Algorithm B1 over a long stream, split into independent chunks of whole
@@ -231,14 +247,18 @@ def polar_window(seed: int, offset: int, j0: int, ncand: int, mu: float = 0.0, s
     return out[:2 * a]
 
 
-def polar_chunk_counts(seed: int, offset: int, ncand: int, chunk: int, threads: int | None = None) -> np.ndarray:
+def polar_chunk_counts(seed: int, offset: int, ncand: int, chunk: int, threads: int | None = None,
+                       kind: str = "polar") -> np.ndarray:
     """Accepted counts of consecutive candidate chunks [c, c + chunk) of the
-    stream, each from one call of the reference count."""
+    stream, each from one call of the reference count of the rejection
+    method `kind` ("polar", "polar2" or "ratio"; two uniforms per candidate
+    in each)."""
     starts = list(range(0, ncand, chunk))
     L = lib()
+    count = {"polar": L.orc_polar_count, "polar2": L.orc_polar2_count, "ratio": L.orc_ratio_count}[kind]
 
     def work(c0):
-        return int(L.orc_polar_count(seed & M64, (offset + 2 * c0) & M64, min(chunk, ncand - c0)))
+        return int(count(seed & M64, (offset + 2 * c0) & M64, min(chunk, ncand - c0)))
 
     with ThreadPoolExecutor(max_workers=threads or os.cpu_count()) as ex:
         return np.array(list(ex.map(work, starts)), dtype=np.int64)

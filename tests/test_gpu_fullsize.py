@@ -6,9 +6,12 @@ the oracle computes independently:
   sampled output indices, each pair from its own counters; Polar on whole
   candidate chunks, placed by the oracle's own prefix of accepted counts,
   plus the consumed count;
+* single streams of 2^30 FP32 normals of P2 (seed 7) and Algorithm R (seed
+  21) on whole candidate chunks placed by the oracle's prefix, with the
+  consumed count, and of B2 and B3 (seed 1) at sampled output indices;
 * the batched workload of 4096 streams (about 4.4e8 normals per method, B1,
-  Polar, P2, B3 and Algorithm R): every stream's consumed count, and sampled
-  streams in full;
+  Polar, P2, B3, Algorithm R and B2): every stream's consumed count, and
+  sampled streams in full;
 * 64 graph-replayed fills of 2^28 FP32 Polar normals from one device cursor
   (2^34 normals of one stream): the final cursor against the oracle's count,
   and sampled slices of sampled fills, placed by the oracle's prefix, with
@@ -67,6 +70,101 @@ class PolarIndex:
         bits = np.unpackbits(masks.view(np.uint8), bitorder="little")
         j = c0 + int(np.flatnonzero(bits)[npairs - 1 - int(self.pref[c])])
         return 2 * (j + 1)
+
+
+class RejIndex:
+    """The oracle's placement of a stream of method P2 or Algorithm R:
+    accepted counts of consecutive candidate chunks, their exclusive prefix,
+    and each chunk's values.  P2 yields a pair per accepted candidate, R one
+    value."""
+
+    RATE = {"polar2": np.pi / 4, "ratio": np.sqrt(np.pi * np.e) / 4}
+
+    def __init__(self, kind, seed, offset, n):
+        self.kind, self.seed, self.offset = kind, seed, offset
+        self.epc = 1 if kind == "ratio" else 2
+        need = (n + self.epc - 1) // self.epc
+        ncand = int(need / self.RATE[kind] * 1.0005) + (1 << 16)
+        while True:
+            counts = O.polar_chunk_counts(seed, offset, ncand, CHUNK, THREADS, kind)
+            if counts.sum() >= need:
+                break
+            ncand += ncand // 8
+        self.ncand, self.need = ncand, need
+        self.pref = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+        self.count = O.ratio_count if kind == "ratio" else O.polar2_count
+        self.win = O.ratio_window if kind == "ratio" else O.polar2_window
+
+    def chunk_of(self, a):
+        return int(np.searchsorted(self.pref, a, side="right")) - 1
+
+    def window(self, c):
+        """Values of chunk c's accepted candidates and the output element
+        index of the first."""
+        c0 = c * CHUNK
+        return self.win(self.seed, self.offset, c0, min(CHUNK, self.ncand - c0)), self.epc * int(self.pref[c])
+
+    def consumed(self):
+        """2 (j + 1) for the candidate j that supplies the last needed
+        accepted candidate, found by bisection on the oracle's counts."""
+        k = self.need - 1
+        c = self.chunk_of(k)
+        c0 = c * CHUNK
+        want = k - int(self.pref[c]) + 1          # accepted candidates needed inside the chunk
+        lo, hi = 1, min(CHUNK, self.ncand - c0)   # count(c0, hi) >= want
+        while lo < hi:
+            mid = (lo + hi) // 2
+            if self.count(self.seed, self.offset + 2 * c0, mid) >= want:
+                hi = mid
+            else:
+                lo = mid + 1
+        return 2 * (c0 + lo)
+
+
+@pytest.mark.parametrize("kind,seed", [("polar2", 7), ("ratio", 21)])
+def test_rejection_single_stream_2e30_sampled(kind, seed):
+    """2^30 FP32 normals of method P2 (seed 7) and Algorithm R (seed 21), the
+    single streams the benchmark times: whole candidate chunks placed by the
+    oracle's own prefix counts (the first, the last and random ones), and the
+    consumed count."""
+    d = dev()
+    n = 1 << 30
+    out = torch.empty(n, dtype=torch.float32, device=d)
+    cons = torch.zeros(1, dtype=torch.int64, device=d)
+    case(kind, "f32 single stream", n)
+    f = nb.nrng_polar2 if kind == "polar2" else nb.nrng_ratio
+    f(seed, 0, n, 0.0, 1.0, out, nb.NRNG_F32, None, cons)
+    torch.cuda.synchronize()
+    ix = RejIndex(kind, seed, 0, n)
+    assert int(u64(cons)[0]) == ix.consumed()
+    last = ix.chunk_of(ix.need - 1)
+    chunks = sorted({0, last} | set(synth.rng(35).integers(0, last, 8).tolist()))
+    for c in chunks:
+        vals, e0 = ix.window(c)
+        m = min(vals.size, n - e0)
+        got = host(out[e0:e0 + m])
+        assert_close(got, vals[:m], nb.NRNG_F32, what="%s 2^30 chunk %d" % (kind, c))
+
+
+@pytest.mark.parametrize("method", ["b2", "b3"])
+def test_box_muller_family_single_stream_2e30_sampled(method):
+    """2^30 FP32 normals of methods B2 and B3 (seed 1, as the benchmark),
+    at sampled output indices, each from its own pair's counters."""
+    d = dev()
+    n = 1 << 30
+    out = torch.empty(n, dtype=torch.float32, device=d)
+    case(method, "f32 single stream", n)
+    (nb.nrng_b2 if method == "b2" else nb.nrng_b3)(1, 0, n, 0.0, 1.0, out, nb.NRNG_F32)
+    torch.cuda.synchronize()
+    idx = np.concatenate([np.arange(64), n - 64 + np.arange(64),
+                          synth.rng(36).integers(0, n, 4096)]).astype(np.int64)
+    got = host(out[torch.from_numpy(idx).to(d)])
+    ref = O.pairs_at(method, 1, 0, idx)
+    extra = None
+    if method == "b2":
+        other = O.pairs_at(method, 1, 0, idx ^ 1)          # the same pair's other value
+        extra = 2.0**-19 * np.hypot(ref, other)
+    assert_close(got, ref, nb.NRNG_F32, what="%s 2^30 sampled" % method, extra=extra)
 
 
 def test_b1_single_stream_2e30_sampled():
