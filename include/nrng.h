@@ -206,10 +206,12 @@ int nrng_polar2(uint64_t seed, uint64_t offset, uint64_t n, double mu, double si
  *   the a-th accepted candidate writes output a = sigma x + mu.
  * (The test is the ratio method's, which gives the 8/sqrt(pi e) = 2.74
  * uniforms per normal that Section 5 states; the inequality as printed there
- * would accept 76% of candidates and not give a normal variable.)  The test
- * is decided in FP64, so accept masks, output indices and consumed counts
- * are exact; values are computed in the output's precision class as for the
- * other methods.  Runs as the Polar kernels (mask, scan, generate) with one
+ * would accept 76% of candidates and not give a normal variable.)  Every
+ * decision equals the FP64 evaluation of the test: an FP32 screen decides
+ * where the two sides differ by more than 16 times its error bound, the FP64
+ * test inside that thin band (under 1e-4 of candidates).  So accept masks,
+ * output indices and consumed counts are exact; values are computed in the
+ * output's precision class as for the other methods.  Runs as the Polar kernels (mask, scan, generate) with one
  * output per accepted candidate.  consumed = 2 (j_last + 1).  Arguments,
  * errors, workspace and launch configuration (nrng_tune_set kernel 1) as
  * nrng_polar. */
