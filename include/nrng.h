@@ -191,13 +191,6 @@ int nrng_polar(uint64_t seed, uint64_t offset, uint64_t n, double mu, double sig
 int nrng_polar2(uint64_t seed, uint64_t offset, uint64_t n, double mu, double sigma, void *out,
                 int dtype, void *stream, uint64_t *d_consumed);
 
-/* Polar method with a device-resident counter offset, for repeated fills
- * captured in a HIP graph: reads the offset from *d_cursor when the kernel
- * runs and advances *d_cursor by the number of uniforms consumed, so that
- * successive calls (or graph replays) continue one stream.  Launches the
- * same three kernels as nrng_polar and allocates nothing once the workspace
- * is reserved (nrng_reserve(n, 0)); NRNG_ECAPTURE otherwise while
- * capturing. */
 /* ------------------------------------------------------------------------
  * Algorithm R (Section 5), the ratio method of Kinderman and Monahan in its
  * basic form, over one stream.  Candidate j uses the uniforms u = u_{2j} and
@@ -211,13 +204,20 @@ int nrng_polar2(uint64_t seed, uint64_t offset, uint64_t n, double mu, double si
  * where the two sides differ by more than 16 times its error bound, the FP64
  * test inside that thin band (under 1e-4 of candidates).  So accept masks,
  * output indices and consumed counts are exact; values are computed in the
- * output's precision class as for the other methods.  Runs as the Polar kernels (mask, scan, generate) with one
- * output per accepted candidate.  consumed = 2 (j_last + 1).  Arguments,
- * errors, workspace and launch configuration (nrng_tune_set kernel 1) as
- * nrng_polar. */
+ * output's precision class as for the other methods.  Runs as the Polar
+ * kernels (mask, scan, generate) with one output per accepted candidate.
+ * consumed = 2 (j_last + 1).  Arguments, errors, workspace and launch
+ * configuration (nrng_tune_set kernel 1) as nrng_polar. */
 int nrng_ratio(uint64_t seed, uint64_t offset, uint64_t n, double mu, double sigma, void *out, int dtype,
                void *stream, uint64_t *d_consumed);
 
+/* Polar method with a device-resident counter offset, for repeated fills
+ * captured in a HIP graph: reads the offset from *d_cursor when the kernel
+ * runs and advances *d_cursor by the number of uniforms consumed, so that
+ * successive calls (or graph replays) continue one stream.  Launches the
+ * same three kernels as nrng_polar and allocates nothing once the workspace
+ * is reserved (nrng_reserve(n, 0)); NRNG_ECAPTURE otherwise while
+ * capturing. */
 int nrng_polar_dev(uint64_t seed, uint64_t *d_cursor, uint64_t n, double mu, double sigma, void *out,
                    int dtype, void *stream);
 
