@@ -35,8 +35,9 @@
  *
  * Precision: NRNG_F64 output is computed in FP64 throughout (the plain FP64
  * kernels).  NRNG_F32, NRNG_BF16 and NRNG_F16 are computed in FP32 (the Polar
- * kernel switches to FP64 for ln(s)/s when s < 2^-20) and rounded to nearest
- * even once into the output format.
+ * kernel switches to FP64 for ln(s)/s when s < 2^-20, and Algorithm R takes
+ * its acceptance decision in FP64 wherever FP32 cannot settle it) and rounded
+ * to nearest even once into the output format.
  *
  * Conventions for every entry point:
  *   - Pointers named out and d_* are device pointers on the current HIP
@@ -48,10 +49,11 @@
  *   - Return value: NRNG_OK (0) or a negative nrng_status.  Argument errors
  *     are reported before anything is launched and nothing is written.
  *     Nothing prints and nothing aborts.
- *   - The library keeps a per-device workspace (Polar accept masks, about one
- *     bit per candidate, tile prefix counts, batched tile tables).  Calls that use it (Polar, batched) must be ordered on one
- *     stream per device; concurrent such calls on different streams of one
- *     device race.  The workspace grows on demand, which allocates; during
+ *   - The library keeps a per-device workspace (accept masks of the rejection
+ *     methods, about one bit per candidate, tile prefix counts, batched tile
+ *     tables).  Calls that use it (Polar, P2, R, batched) must be ordered on
+ *     one stream per device; concurrent such calls on different streams of
+ *     one device race.  The workspace grows on demand, which allocates; during
  *     stream capture growth is refused with NRNG_ECAPTURE, so call
  *     nrng_reserve() before capturing.
  */
