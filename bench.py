@@ -78,6 +78,22 @@ VALU_PEAK_TOPS = 39.32
 #                   doublings (d = 2s, s' = d c, c' = 1 - d s) 12 + 2 FMAs
 ALU_OPS = {"polar_count": 38, "polar_generate": 63, "b1_batched": 67, "p2_count": 37, "p2_generate": 58,
            "b3_batched": 88, "ratio_count": 60, "ratio_generate": 52, "b2_batched": 84}
+# The same counts by instruction class, for weighting by the measured issue
+# cost of each class (extras "valu_issue_cost"): 32-bit multiplies and 64-bit
+# multiply-adds (a hash has 6), 64-bit shifts (2 in a top-word hash, 3 in a
+# full one), 64-bit adds (the counter step), transcendentals (log, sqrt, rcp,
+# sin, cos), and the rest (FMA-like, cost 1).
+ALU_MIX = {
+    "polar_count": {"mul": 14, "shr64": 4, "add64": 2, "trans": 0, "other": 18},
+    "polar_generate": {"mul": 14, "shr64": 4, "add64": 2, "trans": 3, "other": 40},
+    "b1_batched": {"mul": 12, "shr64": 5, "add64": 2, "trans": 4, "other": 44},
+    "p2_count": {"mul": 14, "shr64": 4, "add64": 2, "trans": 0, "other": 17},
+    "p2_generate": {"mul": 14, "shr64": 4, "add64": 2, "trans": 1, "other": 37},
+    "b3_batched": {"mul": 18, "shr64": 8, "add64": 3, "trans": 3, "other": 56},
+    "ratio_count": {"mul": 12, "shr64": 6, "add64": 2, "trans": 2, "other": 38},
+    "ratio_generate": {"mul": 12, "shr64": 6, "add64": 2, "trans": 1, "other": 31},
+    "b2_batched": {"mul": 12, "shr64": 5, "add64": 2, "trans": 2, "other": 63},
+}
 ALU_UNIT = {"polar_count": "candidate", "polar_generate": "output pair", "b1_batched": "output pair",
             "p2_count": "candidate", "p2_generate": "output pair", "b3_batched": "output pair",
             "ratio_count": "candidate", "ratio_generate": "output", "b2_batched": "output pair"}
@@ -307,6 +323,16 @@ def main() -> int:
             if args.only != name:
                 result["extras"][name + "_batched"] = extra_batched(nb, torch, stream, D, ns, total, pairs,
                                                                     args.steps, per_kernel, m)
+        cost = result["extras"]["valu_issue_cost"]
+        w = {"mul": sum(cost[k] for k in ("v_mul_lo_u32", "v_mul_hi_u32", "v_mad_u64_u32", "v_mad_i64_i32")) / 4,
+             "shr64": cost["v_lshrrev_b64"], "add64": cost["v_lshl_add_u64"],
+             "trans": sum(cost[k] for k in ("v_log_f32", "v_sin_f32", "v_sqrt_f32", "v_rcp_f32")) / 4,
+             "other": 1.0}
+        mix = ALU_MIX[dom]
+        wops = sum(mix[c] * w[c] for c in mix)
+        frac_w = roofline["frac"] * wops / ALU_OPS[dom]
+        roofline["issue_weighted"] = {"ops_per_unit": round(wops, 2), "frac": round(frac_w, 4),
+                                      "weights": {k: round(v, 3) for k, v in w.items()}}
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(cfg, [m for m, _ in methods])
     print(json.dumps(result), flush=True)
@@ -397,6 +423,16 @@ def extras(nb, torch, dev, stream, per_kernel, batched_value):
     nh = 1 << 33
     ms = timed(lambda: nb.nrng_probe_hash(1, nh, sink, sink.numel(), stream), 5)
     ex["hash_ceiling_per_s"] = nh / (ms * 1e-3)
+    # issue cost of single VALU instructions, in units of the peak's lane-op
+    # (one FP32 FMA per lane per cycle at 2.4 GHz): whole chip, 8 chains per lane
+    cus = nb.nrng_device_cus()
+    iters = 4096
+    lane_ops = cus * 8 * 256 * 8 * iters
+    vsink = torch.empty(cus * 8 * 256, dtype=torch.int32, device=dev)
+    ex["valu_issue_cost"] = {}
+    for op, name in enumerate(nb.VALU_PROBE_OPS):
+        ms = timed(lambda: nb.nrng_probe_valu(op, iters, vsink, vsink.numel(), stream), 5)
+        ex["valu_issue_cost"][name] = round(VALU_PEAK_TOPS * 1e12 / (lane_ops / (ms * 1e-3)), 3)
 
     # single-stream fills of 2^30 normals (FP32 / BF16 / FP16 / plain FP64)
     n = 1 << 30

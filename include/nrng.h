@@ -363,6 +363,18 @@ int nrng_probe_store(void *out, uint64_t nbytes, void *stream);
 int nrng_probe_copy(void *dst, const void *src, uint64_t nbytes, void *stream);
 int nrng_probe_hash(uint64_t seed, uint64_t nhash, uint64_t *d_sink, uint64_t sink_len, void *stream);
 
+/* Issue-rate probe, for the cost model of the ALU roofline: (device CUs x 8)
+ * workgroups of 256 lanes each run 8 independent chains of `iters`
+ * repetitions of one VALU instruction, then write the xor of their chains to
+ * d_sink[g] (32-bit words, only for g < sink_len).  op selects the
+ * instruction: 0 v_add_u32, 1 v_mul_lo_u32, 2 v_mul_hi_u32, 3 v_mul_u32_u24,
+ * 4 v_fma_f32, 5 v_cvt_f32_u32, 6 v_log_f32, 7 v_sin_f32, 8 v_sqrt_f32,
+ * 9 v_rcp_f32, 10 v_lshrrev_b64, 11 v_lshl_add_u64, 12 v_mad_u64_u32,
+ * 13 v_mad_i64_i32, 14 v_fma_f64.  Lane operations per launch:
+ * CUs x 8 x 256 x 8 x iters.  NRNG_EINVAL for another op, a NULL sink or
+ * sink_len 0. */
+int nrng_probe_valu(int op, uint32_t iters, uint32_t *d_sink, uint64_t sink_len, void *stream);
+
 /* Number of compute units of the current device (0 if none). */
 int nrng_device_cus(void);
 

@@ -61,6 +61,7 @@ _SIGS = {
     "nrng_probe_store": (_i32, [_vp, _u64, _vp]),
     "nrng_probe_copy": (_i32, [_vp, _vp, _u64, _vp]),
     "nrng_probe_hash": (_i32, [_u64, _u64, _vp, _u64, _vp]),
+    "nrng_probe_valu": (_i32, [_i32, ctypes.c_uint32, _vp, _u64, _vp]),
 }
 
 _lock = threading.Lock()
@@ -365,6 +366,17 @@ def nrng_probe_hash(seed, nhash, d_sink, sink_len, stream=None) -> None:
     _need(d_sink, 8 * sink_len, "nrng_probe_hash d_sink")
     _check("nrng_probe_hash", lib().nrng_probe_hash(seed & (2**64 - 1), nhash, _ptr(d_sink), sink_len,
                                                     _stream(stream)))
+
+
+
+VALU_PROBE_OPS = ["v_add_u32", "v_mul_lo_u32", "v_mul_hi_u32", "v_mul_u32_u24", "v_fma_f32", "v_cvt_f32_u32",
+                  "v_log_f32", "v_sin_f32", "v_sqrt_f32", "v_rcp_f32", "v_lshrrev_b64", "v_lshl_add_u64",
+                  "v_mad_u64_u32", "v_mad_i64_i32", "v_fma_f64"]
+
+
+def nrng_probe_valu(op, iters, d_sink, sink_len, stream=None) -> None:
+    _need(d_sink, 4 * sink_len, "nrng_probe_valu d_sink")
+    _check("nrng_probe_valu", lib().nrng_probe_valu(op, iters, _ptr(d_sink), sink_len, _stream(stream)))
 
 
 EXPORTED = sorted(_SIGS)

@@ -13,7 +13,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libnrng.so")
-SOURCES = ["nrng_kernels.hip", "nrng_abi.cpp"]
+SOURCES = ["nrng_kernels.hip", "nrng_probes.hip", "nrng_abi.cpp"]
 HEADERS = ["nrng_device.hpp", "nrng_launch.hpp", "nrng_p2_poly.hpp", "nrng_b2_poly.hpp"]
 ARCH = os.environ.get("NRNG_OFFLOAD_ARCH", "gfx950")
 

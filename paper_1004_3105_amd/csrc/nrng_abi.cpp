@@ -974,4 +974,18 @@ int nrng_probe_hash(uint64_t seed, uint64_t nhash, uint64_t *d_sink, uint64_t si
     return hip_status(launch_probe_hash(seed, nhash, d_sink, sink_len, (uint32_t)grid, S(stream)));
 }
 
+int nrng_probe_valu(int op, uint32_t iters, uint32_t *d_sink, uint64_t sink_len, void *stream)
+{
+    if (op < 0 || op >= kProbeValuOps || !d_sink || sink_len == 0)
+        return NRNG_EINVAL;
+    DevState *d;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        int rc = get_dev(&d);
+        if (rc)
+            return rc;
+    }
+    return hip_status(launch_probe_valu(op, iters, d_sink, sink_len, (uint32_t)d->cus * 8, S(stream)));
+}
+
 }  // extern "C"

@@ -140,3 +140,12 @@ def test_b2_argument_errors():
     assert L.nrng_test_b2_words(None, 4, 0.0, 1.0, p, 1, None) == nb.NRNG_EINVAL
     assert L.nrng_batched(nb.NRNG_METHOD_B2, 4, p, p, p, None, p, p, p, 100, 9, None, None) == nb.NRNG_EDTYPE
     assert L.nrng_batched(6, 4, p, p, p, None, p, p, p, 100, 1, None, None) == nb.NRNG_EINVAL
+
+
+def test_probe_valu_argument_errors():
+    L = nb.lib()
+    p = ctypes.c_void_p(0x1000)
+    assert L.nrng_probe_valu(-1, 16, p, 64, None) == nb.NRNG_EINVAL
+    assert L.nrng_probe_valu(len(nb.VALU_PROBE_OPS), 16, p, 64, None) == nb.NRNG_EINVAL
+    assert L.nrng_probe_valu(0, 16, None, 64, None) == nb.NRNG_EINVAL
+    assert L.nrng_probe_valu(0, 16, p, 0, None) == nb.NRNG_EINVAL
