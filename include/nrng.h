@@ -300,6 +300,15 @@ int nrng_tune_set(int kernel, int dtype, uint32_t wg, uint32_t unroll, uint32_t 
 int nrng_tune_get(int kernel, int dtype, uint32_t *wg, uint32_t *unroll, uint32_t *grid_per_cu);
 int nrng_tune_variants(int kernel, uint32_t *pairs, int max_pairs);
 
+/* Load a launch-configuration table (as written by the autotuner) from a text
+ * file: one entry per line, "<kernel> <dtype> <wg> <unroll> <grid_per_cu>",
+ * kernel one of b1, polar, b1_batched (kernels 0, 1, 2 above), dtype one of
+ * f64, f32, bf16, f16; '#' starts a comment.  All entries are checked first
+ * (names, and (wg, unroll) a compiled variant) and then applied together;
+ * NRNG_EINVAL for a NULL or unreadable path or any bad entry, in which case
+ * nothing is changed.  Entries not in the file keep their values. */
+int nrng_tune_load(const char *path);
+
 /* ------------------------------------------------------------------------
  * Test hooks: the production per-pair arithmetic and compaction fed from
  * explicit inputs instead of the hash stream.

@@ -3,8 +3,9 @@
 For each kernel (B1 single stream, Polar, B1 batched) and output dtype it
 times every compiled (workgroup size, unroll) variant at a few persistent-
 grid caps on a representative workload, keeps the fastest, and writes the
-table to tune_<arch>.json next to this file.  `apply()` loads such a table
-into the library (nrng_tune_set); the binding calls it on first use.
+table to tune_<arch>.json and, in the plain-text form of the C ABI's
+nrng_tune_load, tune_<arch>.txt next to this file.  `apply()` loads such a
+table into the library.
 
 Usage (on the GPU): python -m paper_1004_3105_amd.autotune [--quick]
 """
@@ -26,17 +27,35 @@ def table_path(arch: str = "gfx950") -> str:
     return os.path.join(HERE, "tune_%s.json" % arch)
 
 
+def text_table(tab: dict) -> str:
+    """The table in the plain-text form that the C ABI's nrng_tune_load reads."""
+    lines = ["# kernel dtype wg unroll grid_per_cu  (%s)" % tab.get("arch", "")]
+    for e in tab.get("entries", []):
+        lines.append("%s %s %d %d %d" % (e["kernel"], e["dtype"], e["wg"], e["unroll"], e.get("grid_per_cu", 0)))
+    return "\n".join(lines) + "\n"
+
+
 def apply(path: str | None = None) -> bool:
-    """Load a tune table into the library; False if there is none."""
+    """Load a tune table into the library; False if there is none.  A .txt
+    table goes to the library's own loader; a .json one is converted first."""
     path = path or table_path()
     if not os.path.exists(path):
-        return False
-    with open(path) as f:
-        tab = json.load(f)
-    inv_k = {v: k for k, v in KNAME.items()}
-    inv_d = {v: k for k, v in DNAME.items()}
-    for e in tab.get("entries", []):
-        nb.nrng_tune_set(inv_k[e["kernel"]], inv_d[e["dtype"]], e["wg"], e["unroll"], e.get("grid_per_cu", 0))
+        txt = os.path.splitext(path)[0] + ".txt"
+        if not os.path.exists(txt):
+            return False
+        path = txt
+    if path.endswith(".json"):
+        import tempfile
+        with open(path) as f:
+            tab = json.load(f)
+        with tempfile.NamedTemporaryFile("w", suffix=".txt", delete=False) as t:
+            t.write(text_table(tab))
+        try:
+            nb.nrng_tune_load(t.name)
+        finally:
+            os.unlink(t.name)
+    else:
+        nb.nrng_tune_load(path)
     return True
 
 
@@ -128,6 +147,8 @@ def tune(quick: bool = False, out_path: str | None = None, log=print) -> dict:
     path = out_path or table_path()
     with open(path, "w") as f:
         json.dump(tab, f, indent=1)
+    with open(os.path.splitext(path)[0] + ".txt", "w") as f:
+        f.write(text_table(tab))
     return tab
 
 

@@ -62,6 +62,7 @@ _SIGS = {
     "nrng_probe_copy": (_i32, [_vp, _vp, _u64, _vp]),
     "nrng_probe_hash": (_i32, [_u64, _u64, _vp, _u64, _vp]),
     "nrng_probe_valu": (_i32, [_i32, ctypes.c_uint32, _vp, _u64, _vp]),
+    "nrng_tune_load": (_i32, [ctypes.c_char_p]),
 }
 
 _lock = threading.Lock()
@@ -367,6 +368,10 @@ def nrng_probe_hash(seed, nhash, d_sink, sink_len, stream=None) -> None:
     _check("nrng_probe_hash", lib().nrng_probe_hash(seed & (2**64 - 1), nhash, _ptr(d_sink), sink_len,
                                                     _stream(stream)))
 
+
+
+def nrng_tune_load(path: str) -> None:
+    _check("nrng_tune_load", lib().nrng_tune_load(os.fsencode(path)))
 
 
 VALU_PROBE_OPS = ["v_add_u32", "v_mul_lo_u32", "v_mul_hi_u32", "v_mul_u32_u24", "v_fma_f32", "v_cvt_f32_u32",

@@ -7,6 +7,8 @@
 #include <cstdint>
 #include <cstring>
 #include <mutex>
+#include <cstdio>
+#include <vector>
 
 #include "../../include/nrng.h"
 #include "nrng_launch.hpp"
@@ -789,22 +791,75 @@ int nrng_fillgraph_destroy(void *graph)
     return NRNG_OK;
 }
 
+// Index of the compiled variant (wg, unroll) of a kernel, or -1.
+static int find_variant(int kernel, uint32_t wg, uint32_t unroll)
+{
+    const Variant *v;
+    const int nv = kernel == 1 ? polar_variants(&v) : b1_variants(&v);
+    for (int i = 0; i < nv; ++i)
+        if (v[i].wg == wg && v[i].unroll == unroll)
+            return i;
+    return -1;
+}
+
 int nrng_tune_set(int kernel, int dtype, uint32_t wg, uint32_t unroll, uint32_t grid_per_cu)
 {
     if (kernel < 0 || kernel > 2)
         return NRNG_EINVAL;
     if (!dtype_ok(dtype))
         return NRNG_EDTYPE;
-    const Variant *v;
-    const int nv = kernel == 1 ? polar_variants(&v) : b1_variants(&v);
-    for (int i = 0; i < nv; ++i) {
-        if (v[i].wg == wg && v[i].unroll == unroll) {
-            std::lock_guard<std::mutex> lk(g_mu);
-            g_tune[kernel][dtype] = {i, grid_per_cu};
-            return NRNG_OK;
-        }
+    const int i = find_variant(kernel, wg, unroll);
+    if (i < 0)
+        return NRNG_EINVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_tune[kernel][dtype] = {i, grid_per_cu};
+    return NRNG_OK;
+}
+
+int nrng_tune_load(const char *path)
+{
+    if (!path)
+        return NRNG_EINVAL;
+    std::FILE *f = std::fopen(path, "r");
+    if (!f)
+        return NRNG_EINVAL;
+    struct Entry {
+        int kernel, dtype, vi;
+        uint32_t gpc;
+    };
+    std::vector<Entry> entries;
+    static const char *const knames[] = {"b1", "polar", "b1_batched"};
+    static const char *const dnames[] = {"f64", "f32", "bf16", "f16"};
+    char line[512];
+    int rc = NRNG_OK;
+    while (rc == NRNG_OK && std::fgets(line, sizeof line, f)) {
+        if (char *h = std::strchr(line, '#'))
+            *h = 0;
+        char kn[32], dn[16];
+        unsigned wg, un, gpc;
+        const int got = std::sscanf(line, "%31s %15s %u %u %u", kn, dn, &wg, &un, &gpc);
+        if (got <= 0)
+            continue;   // blank or comment-only line
+        int k = -1, d = -1;
+        for (int i = 0; i < 3; ++i)
+            if (!std::strcmp(kn, knames[i]))
+                k = i;
+        for (int i = 0; i < 4; ++i)
+            if (!std::strcmp(dn, dnames[i]))
+                d = i;
+        const int vi = (got == 5 && k >= 0) ? find_variant(k, wg, un) : -1;
+        if (got != 5 || k < 0 || d < 0 || vi < 0)
+            rc = NRNG_EINVAL;
+        else
+            entries.push_back({k, d, vi, gpc});
     }
-    return NRNG_EINVAL;
+    std::fclose(f);
+    if (rc)
+        return rc;   // nothing applied
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (const Entry &e : entries)
+        g_tune[e.kernel][e.dtype] = {e.vi, e.gpc};
+    return NRNG_OK;
 }
 
 int nrng_tune_get(int kernel, int dtype, uint32_t *wg, uint32_t *unroll, uint32_t *grid_per_cu)

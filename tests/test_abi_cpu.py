@@ -149,3 +149,35 @@ def test_probe_valu_argument_errors():
     assert L.nrng_probe_valu(len(nb.VALU_PROBE_OPS), 16, p, 64, None) == nb.NRNG_EINVAL
     assert L.nrng_probe_valu(0, 16, None, 64, None) == nb.NRNG_EINVAL
     assert L.nrng_probe_valu(0, 16, p, 0, None) == nb.NRNG_EINVAL
+
+
+def test_tune_load_applies_a_valid_table_and_rejects_a_bad_one(tmp_path):
+    from paper_1004_3105_amd import autotune
+    saved = {(k, d): nb.nrng_tune_get(k, d) for k in (0, 1, 2) for d in (0, 1, 2, 3)}
+    try:
+        good = tmp_path / "t.txt"
+        good.write_text("# comment\npolar f32 512 32 3\n\nb1_batched bf16 256 2 0  # trailing\n")
+        nb.nrng_tune_load(str(good))
+        assert nb.nrng_tune_get(1, nb.NRNG_F32) == (512, 32, 3)
+        assert nb.nrng_tune_get(2, nb.NRNG_BF16) == (256, 2, 0)
+        assert nb.nrng_tune_get(0, nb.NRNG_F32) == saved[(0, nb.NRNG_F32)]      # untouched
+        for text in ("polar f32 512 33 0\n", "polar f99 256 32 0\n", "nope f32 256 32 0\n", "polar f32 256\n"):
+            bad = tmp_path / "bad.txt"
+            bad.write_text("b1 f64 256 1 0\n" + text)
+            before = nb.nrng_tune_get(0, nb.NRNG_F64)
+            with pytest.raises(nb.NrngError):
+                nb.nrng_tune_load(str(bad))
+            assert nb.nrng_tune_get(0, nb.NRNG_F64) == before                  # nothing applied
+        with pytest.raises(nb.NrngError):
+            nb.nrng_tune_load(str(tmp_path / "missing.txt"))
+        assert nb.lib().nrng_tune_load(None) == nb.NRNG_EINVAL
+        # the autotuner's text form round-trips through the C loader
+        tab = {"arch": "gfx950", "entries": [{"kernel": "b1", "dtype": "f16", "wg": 512, "unroll": 2,
+                                              "grid_per_cu": 4}]}
+        rt = tmp_path / "rt.txt"
+        rt.write_text(autotune.text_table(tab))
+        assert autotune.apply(str(rt))
+        assert nb.nrng_tune_get(0, nb.NRNG_F16) == (512, 2, 4)
+    finally:
+        for (k, d), v in saved.items():
+            nb.nrng_tune_set(k, d, *v)
