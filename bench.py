@@ -323,6 +323,9 @@ def main() -> int:
             if args.only != name:
                 result["extras"][name + "_batched"] = extra_batched(nb, torch, stream, D, ns, total, pairs,
                                                                     args.steps, per_kernel, m)
+        ceiling = result["extras"]["store_ceiling_GBps"]
+        for pk in per_kernel.values():
+            pk["frac_store_ceiling"] = round(pk["write_GBps"] / ceiling, 4)
         cost = result["extras"]["valu_issue_cost"]
         w = {"mul": sum(cost[k] for k in ("v_mul_lo_u32", "v_mul_hi_u32", "v_mad_u64_u32", "v_mad_i64_i32")) / 4,
              "shr64": cost["v_lshrrev_b64"], "add64": cost["v_lshl_add_u64"],
@@ -516,9 +519,17 @@ def cpu_baseline(cfg, methods):
     with ThreadPoolExecutor(max_workers=cores) as ex:
         done = sum(ex.map(work, jobs, chunksize=8))
     dt = time.perf_counter() - t0
+    # the same oracle on one thread, on the two small parity configurations:
+    # B1 FP64 seed 1, 2^20 normals; Polar seed 7, 2^24 normals
+    single = {}
+    for key, fn, seed, n in (("b1_2^20", O.b1, 1, 1 << 20), ("polar_2^24", O.polar, 7, 1 << 24)):
+        t1 = time.perf_counter()
+        fn(seed, 0, n)
+        single[key + "_normals_per_s"] = n / (time.perf_counter() - t1)
     return {"value": done / dt, "unit": "normals/s", "cores": cores, "kind": "oracle",
             "sample": "the whole batched workload: %d streams x %s, %d normals, one FP64 oracle call per "
-                      "stream on a %d-thread pool (%.1f s wall)" % (ns, "+".join(methods), done, cores, dt)}
+                      "stream on a %d-thread pool (%.1f s wall)" % (ns, "+".join(methods), done, cores, dt),
+            "single_thread": single}
 
 
 if __name__ == "__main__":
