@@ -5,7 +5,8 @@ the oracle computes independently:
 * single streams of 2^30 FP32 normals (B1 seed 1, Polar seed 7): B1 at
   sampled output indices, each pair from its own counters; Polar on whole
   candidate chunks, placed by the oracle's own prefix of accepted counts,
-  plus the consumed count;
+  plus the consumed count; and both in full, every value against the
+  oracle's whole stream;
 * single streams of 2^30 FP32 normals of P2 (seed 7) and Algorithm R (seed
   21) on whole candidate chunks placed by the oracle's prefix, with the
   consumed count, and of B2 and B3 (seed 1) at sampled output indices;
@@ -119,6 +120,39 @@ class RejIndex:
             else:
                 lo = mid + 1
         return 2 * (c0 + lo)
+
+
+@pytest.mark.parametrize("method,seed", [("b1", 1), ("polar", 7)])
+def test_full_stream_error_2e30(method, seed, capsys):
+    """Every one of the 2^30 FP32 values of the B1 (seed 1) and Polar (seed 7)
+    streams against the oracle's whole stream (computed in chunks on the host
+    threads), compared chunk by chunk; the worst error is printed."""
+    d = dev()
+    n = 1 << 30
+    out = torch.empty(n, dtype=torch.float32, device=d)
+    cons = torch.zeros(1, dtype=torch.int64, device=d)
+    case(method, "f32 single stream, full comparison", n)
+    if method == "b1":
+        nb.nrng_boxmuller(seed, 0, n, 0.0, 1.0, out, nb.NRNG_F32)
+    else:
+        nb.nrng_polar(seed, 0, n, 0.0, 1.0, out, nb.NRNG_F32, None, cons)
+    torch.cuda.synchronize()
+    if method == "b1":
+        ref, used = O.b1_parallel(seed, 0, n, threads=THREADS), 2 * (n // 2)
+    else:
+        ref, used = O.polar_parallel(seed, 0, n, threads=THREADS)
+        assert int(u64(cons)[0]) == used
+    worst, rel = 0.0, 0.0
+    step = 1 << 26
+    for c0 in range(0, n, step):
+        z = host(out[c0:c0 + step])
+        r = ref[c0:c0 + step]
+        worst = max(worst, assert_close(z, r, nb.NRNG_F32, what="%s 2^30 full, chunk at %d" % (method, c0)))
+        rel = max(rel, float(np.max(np.abs(z - r) / np.maximum(1.0, np.abs(r)))))
+    del ref
+    with capsys.disabled():
+        print("\n[%s FP32, all 2^30 values] max|dz|/max(1,|z|) %.3e, max err/bar %.3f" % (method, rel, worst),
+              flush=True)
 
 
 @pytest.mark.parametrize("kind,seed", [("polar2", 7), ("ratio", 21)])
