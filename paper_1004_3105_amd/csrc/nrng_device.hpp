@@ -379,7 +379,10 @@ __device__ __forceinline__ double ln_u64_small(uint64_t S)
     return 2.0 * t * p + (double)e * 0.69314718055994530942;
 }
 
-__device__ __forceinline__ float polar_r_small(uint64_t S, float sigma)
+// Kept out of line: it runs for about one pair in 10^6, and inlined at its
+// two call sites its FP64 temporaries would raise the register count of the
+// whole generate kernel (and so lower its occupancy) for every pair.
+__device__ __attribute__((noinline)) float polar_r_small(uint64_t S, float sigma)
 {
     const double s = (double)S * 0x1p-62;                   // exact
     const double ln_s = ln_u64_small(S) - 62.0 * 0.69314718055994530942;
