@@ -591,7 +591,11 @@ __device__ __forceinline__ float polar2_r31_f32(uint64_t S, float ks31, float k2
 // The test is decided in FP64 (the paper's precision), in the oracle's order
 // of operations; c is sqrt(8.0 / e) rounded as the host computes it.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ bool ratio_accept(uint64_t ku, uint64_t kv, double c)
+// Kept out of line: the kernels call it only inside the FP32 screen's band
+// (ratio_accept_screened) and on the serial continuation path, and inlined
+// its FP64 logarithm would raise the register count of the mask and
+// generate kernels for every candidate.
+__device__ __attribute__((noinline)) bool ratio_accept(uint64_t ku, uint64_t kv, double c)
 {
 #pragma clang fp contract(off)
     const double u = (double)(ku >> 11) * 0x1p-53;
