@@ -210,3 +210,42 @@ def test_exec_parts_equal_exec(method):
     with pytest.raises(nb.NrngError):
         nb.nrng_batched_exec_part(3, method, ns, D["seed"], D["offset"], D["n"], None, D["mu"], D["sigma"],
                                   outs[0][0], nb.NRNG_F32, None, None)
+
+
+@pytest.mark.parametrize("method", [nb.NRNG_METHOD_B1, nb.NRNG_METHOD_POLAR, nb.NRNG_METHOD_P2,
+                                    nb.NRNG_METHOD_B3, nb.NRNG_METHOD_R, nb.NRNG_METHOD_B2])
+def test_batched_plan_and_exec_under_torch_graph_capture(method):
+    """A whole batched call (plan + exec) captured once in a HIP graph (torch's
+    graph API) and replayed three times, with eager work between the replays
+    and the outputs cleared before each: every replay equals the eager call
+    bit for bit, consumed counts included."""
+    d = dev()
+    cfg = small_config(97)
+    D = to_dev(cfg, d)
+    ns, total = len(cfg["n"]), cfg["total"]
+    nb.nrng_reserve(total, ns)
+    out = torch.empty(total, dtype=torch.float32, device=d)
+    cons = torch.zeros(ns, dtype=torch.int64, device=d)
+    case("batched eager before capture", method)
+    nb.nrng_batched(method, ns, D["seed"], D["offset"], D["n"], None, D["mu"], D["sigma"], out, total,
+                    nb.NRNG_F32, None, cons)
+    torch.cuda.synchronize()
+    ref, ref_cons = out.clone(), cons.clone()
+    s = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    case("batched capture", method)
+    with torch.cuda.graph(g, stream=s):
+        nb.nrng_batched(method, ns, D["seed"], D["offset"], D["n"], None, D["mu"], D["sigma"], out, total,
+                        nb.NRNG_F32, s, cons)
+    for r in range(3):
+        out.fill_(float("nan"))
+        cons.zero_()
+        torch.cuda.synchronize()
+        case("batched replay", method, r)
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref), r
+        assert torch.equal(cons, ref_cons), r
+        y = torch.ones(1 << 16, device=d).sum()           # eager work between replays
+        torch.cuda.synchronize()
+        del y
