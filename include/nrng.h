@@ -49,6 +49,10 @@
  *   - Return value: NRNG_OK (0) or a negative nrng_status.  Argument errors
  *     are reported before anything is launched and nothing is written.
  *     Nothing prints and nothing aborts.
+ *   - Sizes: n <= 2^62 for the Box-Muller family (B1, B2, B3); n <= 2^41 for
+ *     the rejection methods (Polar, P2, R) and out_len <= 2^41 for a batch
+ *     (their workspace holds one mask bit per candidate).  Larger sizes
+ *     return NRNG_ERANGE before any launch.
  *   - The library keeps a per-device workspace (accept masks of the rejection
  *     methods, about one bit per candidate, tile prefix counts, batched tile
  *     tables).  Calls that use it (Polar, P2, R, batched) must be ordered on

@@ -66,8 +66,15 @@ def test_argument_errors_return_before_any_launch():
     assert L.nrng_batched(0, 0, None, None, None, None, None, None, None, 0, 1, None, None) == nb.NRNG_OK
     assert L.nrng_batched(1, 4, None, p, p, None, p, p, p, 100, 1, None, None) == nb.NRNG_EINVAL
     assert L.nrng_batched(1, 4, p, p, p, None, p, p, None, 100, 1, None, None) == nb.NRNG_EINVAL
-    # sizes beyond the supported range
+    # sizes beyond the supported range: 2^41 values for the rejection methods
+    # and for a batch's output, 2^62 for the Box-Muller family
     assert L.nrng_polar(1, 0, (1 << 41) + 1, 0.0, 1.0, p, 1, None, None) == nb.NRNG_ERANGE
+    assert L.nrng_polar2(1, 0, (1 << 41) + 1, 0.0, 1.0, p, 1, None, None) == nb.NRNG_ERANGE
+    assert L.nrng_ratio(1, 0, (1 << 41) + 1, 0.0, 1.0, p, 1, None, None) == nb.NRNG_ERANGE
+    for fn in (L.nrng_boxmuller, L.nrng_b3, L.nrng_b2):
+        assert fn(1, 0, (1 << 62) + 1, 0.0, 1.0, p, 1, None) == nb.NRNG_ERANGE
+    for m in range(6):
+        assert L.nrng_batched(m, 4, p, p, p, None, p, p, p, (1 << 41) + 1, 1, None, None) == nb.NRNG_ERANGE
     # test hooks
     assert L.nrng_test_polar_budget(1, 0, 10, 0.0, 1.0, p, 1, 0, None, None) == nb.NRNG_EINVAL
     assert L.nrng_test_polar_xy(None, 8, 0.0, 1.0, p, 1, p, p, None) == nb.NRNG_EINVAL
