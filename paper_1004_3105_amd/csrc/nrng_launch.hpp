@@ -74,7 +74,7 @@ struct B1Args {
 };
 
 struct PrepArgs {
-    int method;                      // 0 = B1, 1 = Polar, 2 = P2, 3 = B3, 4 = Algorithm R
+    int method;                      // 0 = B1, 1 = Polar, 2 = P2, 3 = B3, 4 = Algorithm R, 5 = B2
     uint32_t nstreams;
     const uint64_t *ns, *out_off;    // out_off nullable (packed)
     uint64_t out_len;

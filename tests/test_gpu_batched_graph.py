@@ -71,6 +71,50 @@ def test_batched_packed_matches_single_streams(method, dtype):
                          what="batched stream %d" % j)
 
 
+@pytest.mark.parametrize("method", [nb.NRNG_METHOD_B1, nb.NRNG_METHOD_POLAR, nb.NRNG_METHOD_R])
+def test_batched_many_streams_across_setup_chunks(method):
+    """8315 streams: the set-up kernel takes streams in chunks of 4096 and
+    carries both prefixes (packed output offsets and the tile table) from
+    chunk to chunk.  The packed call equals the same call with explicit
+    offsets element for element, and the streams at the chunk boundaries,
+    plus a random sample, equal single-stream calls bit for bit, consumed
+    counts included."""
+    d = dev()
+    ns = 2 * 4096 + 123
+    cfg = synth.batched_streams(nstreams=ns, seed=0xC4A1, n_lo=1, n_hi=600)
+    cfg["n"][[4095, 8192]] = 0          # empty streams on both sides of a chunk boundary
+    cfg["out_off"] = np.concatenate([[0], np.cumsum(cfg["n"][:-1])]).astype(np.uint64)
+    total = int(cfg["n"].sum())
+    D = to_dev(cfg, d)
+    res = []
+    for packed in (True, False):
+        out = torch.full((total,), float("nan"), dtype=torch.float32, device=d)
+        cons = torch.zeros(ns, dtype=torch.int64, device=d)
+        off = None if packed else torch.from_numpy(cfg["out_off"].view(np.int64)).to(d)
+        case("batched across set-up chunks", method, "packed", packed, ns, total)
+        nb.nrng_batched(method, ns, D["seed"], D["offset"], D["n"], off, D["mu"], D["sigma"], out, total,
+                        nb.NRNG_F32, None, cons)
+        torch.cuda.synchronize()
+        res.append((out, u64(cons)))
+    (out, c), (out_x, c_x) = res
+    assert not torch.isnan(out).any()
+    assert torch.equal(out, out_x)
+    assert np.array_equal(c, c_x)
+    name = {nb.NRNG_METHOD_B1: "b1", nb.NRNG_METHOD_POLAR: "polar", nb.NRNG_METHOD_R: "ratio"}[method]
+    edges = [0, 1, 4094, 4095, 4096, 4097, 8191, 8192, 8193, ns - 1]
+    sample = sorted(set(edges) | set(int(j) for j in synth.rng(17).integers(0, ns, 24)))
+    for j in sample:
+        n = int(cfg["n"][j])
+        o0 = int(cfg["out_off"][j])
+        single, used = run(name, int(cfg["seed"][j]), int(cfg["offset"][j]), n, nb.NRNG_F32,
+                           float(cfg["mu"][j]), float(cfg["sigma"][j]), with_consumed=True)
+        assert torch.equal(out[o0:o0 + n], single), j
+        if name == "b1":
+            assert c[j] == 2 * ((n + 1) // 2), j
+        else:
+            assert c[j] == (used if n > 0 else 0), j
+
+
 @pytest.mark.parametrize("method", [nb.NRNG_METHOD_B1, nb.NRNG_METHOD_POLAR])
 def test_batched_explicit_offsets_and_invalid_streams(method):
     d = dev()
