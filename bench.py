@@ -46,8 +46,9 @@ VALU_PEAK_TOPS = 39.32
 #                   0 < S < 2^62 test 2
 #   polar_generate: per pair: 2 hashes 34 + S 2 + the FP32 radius with the
 #                   exact complement near s = 1 (complement and select 5,
-#                   conversion 4, remainder and selects 7, log / rcp / sqrt
-#                   3, scalings 4) 23 + 2 conversions and 2 FMAs 4
+#                   conversion 4, remainder and selects 7, log and
+#                   reciprocal square root 2, scalings 4) 22 + 2 conversions
+#                   and 2 FMAs 4
 #   b1_batched:     per pair: hash of u 18 + hash of v (top word) 17 +
 #                   ln(1 - u) with the exact complement 21 + angle reduction,
 #                   conversion, sin, cos 9 + 2 FMAs
@@ -76,16 +77,16 @@ VALU_PEAK_TOPS = 39.32
 #                   reduction, conversion and scaling of y 6 + t = y^2 and
 #                   the two polynomials (6 FMAs, 1 product) 8 + four
 #                   doublings (d = 2s, s' = d c, c' = 1 - d s) 12 + 2 FMAs
-ALU_OPS = {"polar_count": 38, "polar_generate": 63, "b1_batched": 67, "p2_count": 37, "p2_generate": 58,
+ALU_OPS = {"polar_count": 38, "polar_generate": 62, "b1_batched": 67, "p2_count": 37, "p2_generate": 58,
            "b3_batched": 88, "ratio_count": 60, "ratio_generate": 52, "b2_batched": 84}
 # The same counts by instruction class, for weighting by the measured issue
 # cost of each class (extras "valu_issue_cost"): 32-bit multiplies and 64-bit
 # multiply-adds (a hash has 6), 64-bit shifts (2 in a top-word hash, 3 in a
 # full one), 64-bit adds (the counter step), transcendentals (log, sqrt, rcp,
-# sin, cos), and the rest (FMA-like, cost 1).
+# rsq, sin, cos), and the rest (FMA-like, cost 1).
 ALU_MIX = {
     "polar_count": {"mul": 14, "shr64": 4, "add64": 2, "trans": 0, "other": 18},
-    "polar_generate": {"mul": 14, "shr64": 4, "add64": 2, "trans": 3, "other": 40},
+    "polar_generate": {"mul": 14, "shr64": 4, "add64": 2, "trans": 2, "other": 40},
     "b1_batched": {"mul": 12, "shr64": 5, "add64": 2, "trans": 4, "other": 44},
     "p2_count": {"mul": 14, "shr64": 4, "add64": 2, "trans": 0, "other": 17},
     "p2_generate": {"mul": 14, "shr64": 4, "add64": 2, "trans": 1, "other": 37},

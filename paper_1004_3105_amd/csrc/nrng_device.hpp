@@ -336,9 +336,13 @@ __device__ __forceinline__ void polar_value_f64(int32_t X, int32_t Y, uint64_t S
 //    ln(s) = ln(y) + e (2 - y), as in B1 above.  This keeps ln(s) accurate
 //    as s -> 1, where ln(s) cancels.
 //  * s < 2^-20 (S < 2^42): ln(s)/s is evaluated in FP64 (exact s; rare).
-//  * r = sqrt(log2(s) * (-2 ln 2 sigma^2) / s); z = r x + mu by an FMA.
-// FP32 radius factor r = sigma sqrt(-2 ln(s) / s) for S >= 2^42.
-__device__ __forceinline__ float polar_r_f32(uint64_t S, float k2)
+//  * With l2 = log2(s) (negative for every accepted S), r^2 = -2 ln 2 l2 / s,
+//    so sigma r 2^-31 = (l2 kr) / sqrt(-l2 s) with the per-launch constant
+//    kr = -sigma sqrt(2 ln 2) 2^-31: one reciprocal square root where
+//    r = sqrt(l2 k / s) takes a reciprocal and a square root.  Then
+//    z = (sigma r 2^-31) X + mu by an FMA (X as an integer, converted).
+// FP32 sigma r 2^-31, r = sqrt(-2 ln(s) / s), for S >= 2^42.
+__device__ __forceinline__ float polar_r31_f32(uint64_t S, float kr)
 {
     // q = S for s <= 1/2, q = 2^62 - S = d 2^62 (exact) for s > 1/2
     const bool high = S > (1ull << 61);
@@ -349,7 +353,7 @@ __device__ __forceinline__ float polar_r_f32(uint64_t S, float k2)
     const float sf = high ? yv : qf;
     const float corr = high ? e * (2.0f - yv) : 0.0f;
     const float l2 = __builtin_fmaf(corr, 1.4426950408889634f, __builtin_amdgcn_logf(sf));
-    return __builtin_amdgcn_sqrtf(l2 * k2 * __builtin_amdgcn_rcpf(sf));
+    return (l2 * kr) * __builtin_amdgcn_rsqf(-(l2 * sf));
 }
 
 // The same for S < 2^42 (s < 2^-20), evaluated in FP64 with s exact.
@@ -392,12 +396,12 @@ __device__ __attribute__((noinline)) float polar_r_small(uint64_t S, float sigma
 
 __device__ __forceinline__ bool polar_small(uint64_t S) { return (uint32_t)(S >> 32) < (1u << 10); }   // S < 2^42
 
-__device__ __forceinline__ void polar_value_f32(int32_t X, int32_t Y, uint64_t S, float mu, float k2,
+__device__ __forceinline__ void polar_value_f32(int32_t X, int32_t Y, uint64_t S, float mu, float kr,
                                                 float sigma, float& zx, float& zy)
 {
-    const float r = polar_small(S) ? polar_r_small(S, sigma) : polar_r_f32(S, k2);
-    zx = __builtin_fmaf(r, (float)X * 0x1p-31f, mu);
-    zy = __builtin_fmaf(r, (float)Y * 0x1p-31f, mu);
+    const float r31 = polar_small(S) ? polar_r_small(S, sigma) * 0x1p-31f : polar_r31_f32(S, kr);
+    zx = __builtin_fmaf(r31, (float)X, mu);
+    zy = __builtin_fmaf(r31, (float)Y, mu);
 }
 
 // a in the lanes whose bit of m is clear, b in the others.  Written as the
@@ -559,15 +563,17 @@ __device__ __forceinline__ void polar2_value_f64(int32_t X, int32_t Y, uint64_t 
 }
 
 // FP32 radius factor times 2^-31: sigma sqrt(2) g(s) 2^-31.  ks31 =
-// sigma sqrt(2) 2^-31 and k2 = -2 ln 2 sigma^2.  Both branches are formed
-// in every lane and one is selected.
+// sigma sqrt(2) 2^-31 and kr = -sigma sqrt(2 ln 2) 2^-31.  Both branches
+// are formed in every lane and one is selected.
 //  * s <= 8/9: s from the top word of S (absolute error below 2^-30; h has
 //    no singularity there, so only absolute accuracy matters), v by one
 //    reciprocal, h by Horner's rule with the degree-9 coefficients.
 //  * s > 8/9: 1 - s = (2^62 - S) 2^-62 exactly, rounded once, so
-//    -ln(1 - s) has full relative accuracy, and
-//    g(s) sqrt(2) sigma = sqrt(log2(1 - s) k2 / s).
-__device__ __forceinline__ float polar2_r31_f32(uint64_t S, float ks31, float k2)
+//    -ln(1 - s) has full relative accuracy.  With l = log2(1 - s) < 0,
+//    sigma sqrt(2) g(s) = sigma sqrt(2 ln 2) sqrt(-l / s), and
+//    sigma sqrt(2) g(s) 2^-31 = (l kr) / sqrt(-l s): one reciprocal square
+//    root instead of a reciprocal and a square root.
+__device__ __forceinline__ float polar2_r31_f32(uint64_t S, float ks31, float kr)
 {
     const float hf = cvt_f32_u32((uint32_t)(S >> 32));     // S 2^-32 = s 2^30
     const float num = __builtin_fmaf(hf, 6.0f * 0x1p-30f, -4.0f);
@@ -579,8 +585,9 @@ __device__ __forceinline__ float polar2_r31_f32(uint64_t S, float ks31, float k2
         h = __builtin_fmaf(h, v, kP2PolyF32[k]);
     const float tf = u64_to_f32_scaled((1ull << 62) - S, 0x1p-30f, 0x1p-62f);   // 1 - s
     const float sf = hf * 0x1p-30f;
-    const float rl = __builtin_amdgcn_sqrtf(__builtin_amdgcn_logf(tf) * k2 * __builtin_amdgcn_rcpf(sf));
-    return select_lanes(__ballot(polar2_big(S)), h * ks31, rl * 0x1p-31f);
+    const float l = __builtin_amdgcn_logf(tf);
+    const float rl31 = (l * kr) * __builtin_amdgcn_rsqf(-(l * sf));
+    return select_lanes(__ballot(polar2_big(S)), h * ks31, rl31);
 }
 
 // ---------------------------------------------------------------------------
