@@ -218,19 +218,28 @@ int nrng_ratio(uint64_t seed, uint64_t offset, uint64_t n, double mu, double sig
                void *stream, uint64_t *d_consumed);
 
 /* Polar method with a device-resident counter offset, for repeated fills
- * captured in a HIP graph: reads the offset from *d_cursor when the kernel
- * runs and advances *d_cursor by the number of uniforms consumed, so that
- * successive calls (or graph replays) continue one stream.  Launches the
- * same three kernels as nrng_polar and allocates nothing once the workspace
- * is reserved (nrng_reserve(n, 0)); NRNG_ECAPTURE otherwise while
- * capturing. */
+ * captured in a HIP graph.  Section 4 notes that a compressing Polar
+ * routine cannot tell in advance how many normals one vector of candidates
+ * yields, and hides this behind a level of buffering (its user routine
+ * RANN3 around the vector kernel RANN3B).  Here the stream position is kept
+ * instead: the call reads the offset from *d_cursor when the kernel runs
+ * and advances *d_cursor by the number of uniforms consumed, so that
+ * successive calls (or graph replays) continue one stream and each yields
+ * exactly n normals.  Launches the same three kernels as nrng_polar and
+ * allocates nothing once the workspace is reserved (nrng_reserve(n, 0));
+ * NRNG_ECAPTURE otherwise while capturing. */
 int nrng_polar_dev(uint64_t seed, uint64_t *d_cursor, uint64_t n, double mu, double sigma, void *out,
                    int dtype, void *stream);
 
 /* ------------------------------------------------------------------------
- * Many independent streams in one launch sequence: one small set-up kernel
- * builds the tile table on the device, then one persistent B1 kernel, or
- * the three Polar kernels, cover every stream.
+ * Many independent streams in one launch sequence.  Each stream is one call
+ * of a single-stream method (B1 or P of Section 2, B2 or B3 of Section 3,
+ * P2 of Section 4, R of Section 5); the paper's timings assume long vectors
+ * (Section 3: many numbers generated per call), and serving thousands of
+ * short, uneven streams in one launch recovers that on the GPU.  One small
+ * set-up kernel builds the tile table on the device, then one persistent
+ * kernel of the Box-Muller family, or the three Polar kernels, cover every
+ * stream.
  *   method       NRNG_METHOD_B1, NRNG_METHOD_POLAR, NRNG_METHOD_P2, NRNG_METHOD_B3, NRNG_METHOD_R or
  *                NRNG_METHOD_B2
  *   nstreams     number of streams (0 is a no-op)
@@ -238,16 +247,21 @@ int nrng_polar_dev(uint64_t seed, uint64_t *d_cursor, uint64_t n, double mu, dou
  *   d_out_off[j] element offset of stream j's output in `out`; NULL means
  *                packed (exclusive prefix sum of d_n)
  *   d_mu[j], d_sigma[j]             per-stream mean and standard deviation
- *   out, out_len output buffer and its length in elements; streams whose
- *                range [out_off, out_off + n) does not fit are skipped
+ *   out, out_len output buffer and its length in elements; a stream whose
+ *                range [out_off, out_off + n) does not lie in [0, out_len)
+ *                is skipped (invalid)
  *   d_consumed   optional (may be NULL): d_consumed[j] receives stream j's
  *                consumed uniforms, or UINT64_MAX if the stream was skipped.
- * Stream j's values equal those of nrng_boxmuller / nrng_polar / nrng_polar2 / nrng_b3 / nrng_ratio / nrng_b2
- * called alone
- * with (d_seed[j], d_offset[j], d_n[j], d_mu[j], d_sigma[j]), bit for bit.
- * The total of d_n over valid streams must not exceed out_len; otherwise the
- * device-side check fails the whole call (every d_consumed[j] = UINT64_MAX,
- * nothing written).  Per-stream mu and sigma are not validated on the host. */
+ * Stream j's values equal those of nrng_boxmuller / nrng_polar / nrng_polar2 /
+ * nrng_b3 / nrng_ratio / nrng_b2 called alone with (d_seed[j], d_offset[j],
+ * d_n[j], d_mu[j], d_sigma[j]), bit for bit.
+ * The set-up kernel fails the whole call on the device (every d_consumed[j]
+ * = UINT64_MAX, nothing written) when the lengths of the valid streams total
+ * more than out_len (possible only with explicit, overlapping d_out_off), or
+ * when the tile table outgrows the workspace sized for out_len.  Valid
+ * streams with overlapping ranges that pass this check are written in an
+ * unspecified order.  Per-stream mu and sigma are not validated on the
+ * host. */
 int nrng_batched(int method, uint32_t nstreams, const uint64_t *d_seed, const uint64_t *d_offset,
                  const uint64_t *d_n, const uint64_t *d_out_off, const double *d_mu, const double *d_sigma,
                  void *out, uint64_t out_len, int dtype, void *stream, uint64_t *d_consumed);

@@ -36,7 +36,7 @@ def small_config(nstreams=97):
 
 
 @pytest.mark.parametrize("method", [nb.NRNG_METHOD_B1, nb.NRNG_METHOD_POLAR])
-@pytest.mark.parametrize("dtype", [nb.NRNG_F64, nb.NRNG_F32, nb.NRNG_BF16])
+@pytest.mark.parametrize("dtype", [nb.NRNG_F64, nb.NRNG_F32, nb.NRNG_BF16, nb.NRNG_F16])
 def test_batched_packed_matches_single_streams(method, dtype):
     d = dev()
     cfg = small_config()
@@ -172,6 +172,63 @@ def test_batched_overflowing_total_is_rejected_on_device():
     # packed layout: the streams that fit are produced, the last one is skipped
     assert c[-1] == U64MAX
     assert all(x != U64MAX for x in c[:-1])
+
+
+@pytest.mark.parametrize("method", [nb.NRNG_METHOD_B1, nb.NRNG_METHOD_POLAR])
+def test_batched_huge_length_inside_a_setup_group(method):
+    """A packed batch whose sixth stream has n = 2^64 - 1: the set-up kernel
+    sums the lengths of four consecutive streams per thread, so the packed
+    prefix saturates inside the group of streams 4..7.  Streams 0..4 keep
+    their exact offsets (0, 10, 30, 35, 42) and equal single-stream calls bit
+    for bit; the huge stream and every stream after it (whose packed offsets
+    saturate) are skipped, and nothing beyond the valid ranges is written."""
+    d = dev()
+    lens = np.array([10, 20, 5, 7, 3, U64MAX, 4, 6, 9, 1], dtype=np.uint64)
+    ns = len(lens)
+    cfg = {"n": lens, "seed": (np.arange(ns, dtype=np.uint64) * 7919 + 5).astype(np.uint64),
+           "offset": np.zeros(ns, dtype=np.uint64), "mu": np.linspace(-1.0, 1.0, ns),
+           "sigma": np.linspace(0.5, 2.0, ns)}
+    D = to_dev(cfg, d)
+    out_len = 64
+    out = torch.full((out_len,), -777.0, dtype=torch.float32, device=d)
+    cons = torch.zeros(ns, dtype=torch.int64, device=d)
+    case("batched huge length", method)
+    nb.nrng_batched(method, ns, D["seed"], D["offset"], D["n"], None, D["mu"], D["sigma"], out, out_len,
+                    nb.NRNG_F32, None, cons)
+    torch.cuda.synchronize()
+    c = u64(cons)
+    name = "b1" if method == nb.NRNG_METHOD_B1 else "polar"
+    starts = [0, 10, 30, 35, 42]
+    for j, o0 in enumerate(starts):
+        nj = int(lens[j])
+        single, used = run(name, int(cfg["seed"][j]), 0, nj, nb.NRNG_F32, float(cfg["mu"][j]),
+                           float(cfg["sigma"][j]), with_consumed=True)
+        assert torch.equal(out[o0:o0 + nj], single), j
+        assert c[j] == (2 * ((nj + 1) // 2) if name == "b1" else used), j
+    assert all(c[j] == U64MAX for j in range(5, ns))
+    assert torch.all(out[45:] == -777.0)
+
+
+@pytest.mark.parametrize("method", [nb.NRNG_METHOD_B1, nb.NRNG_METHOD_POLAR])
+def test_batched_overlapping_total_is_rejected_on_device(method):
+    """Explicit offsets that place four valid streams of 100 over one buffer
+    of 150: each range fits, but their lengths total 400 > out_len, so the
+    set-up kernel fails the whole call (every consumed count UINT64_MAX,
+    nothing written)."""
+    d = dev()
+    ns = 4
+    cfg = {"n": np.full(ns, 100, dtype=np.uint64), "seed": np.arange(1, ns + 1, dtype=np.uint64),
+           "offset": np.zeros(ns, dtype=np.uint64), "mu": np.zeros(ns), "sigma": np.ones(ns)}
+    D = to_dev(cfg, d)
+    off = torch.from_numpy(np.array([0, 50, 25, 0], dtype=np.int64)).to(d)
+    out = torch.full((150,), -777.0, dtype=torch.float32, device=d)
+    cons = torch.zeros(ns, dtype=torch.int64, device=d)
+    case("batched overlapping total", method)
+    nb.nrng_batched(method, ns, D["seed"], D["offset"], D["n"], off, D["mu"], D["sigma"], out, 150,
+                    nb.NRNG_F32, None, cons)
+    torch.cuda.synchronize()
+    assert all(x == U64MAX for x in u64(cons))
+    assert torch.all(out == -777.0)
 
 
 def test_fillgraph_repeated_fills_continue_one_stream():
