@@ -231,6 +231,24 @@ int nrng_ratio(uint64_t seed, uint64_t offset, uint64_t n, double mu, double sig
 int nrng_polar_dev(uint64_t seed, uint64_t *d_cursor, uint64_t n, double mu, double sigma, void *out,
                    int dtype, void *stream);
 
+/* Algorithm P over one stream without any allocation, for callers that
+ * cannot allocate device memory: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc.  Same arguments, results
+ * (bit for bit), consumed count and launch configuration as nrng_polar, but
+ * the Polar kernels take their workspace from a fixed scratch array of
+ * 8 MiB in device memory (one per device, held until the process ends)
+ * instead of the library's growable workspace, so the call never calls
+ * hipMalloc or hipFree, on its first call included.
+ *   n  at most 2^26 (67,108,864) normals; larger n returns NRNG_ERANGE
+ *      before anything is launched.
+ * The scratch keeps the last call's contents and needs no clearing (every
+ * kernel writes what the next one reads).  All calls of this entry point on
+ * one device share that device's scratch: calls that overlap on one device
+ * (on different streams, or from different host threads without ordering)
+ * race and must not be made. */
+int nrng_polar_noalloc(uint64_t seed, uint64_t offset, uint64_t n, double mu, double sigma, void *out,
+                       int dtype, void *stream, uint64_t *d_consumed);
+
 /* ------------------------------------------------------------------------
  * Many independent streams in one launch sequence.  Each stream is one call
  * of a single-stream method (B1 or P of Section 2, B2 or B3 of Section 3,

@@ -38,6 +38,7 @@ _SIGS = {
     "nrng_polar2": (_i32, [_u64, _u64, _u64, _f64, _f64, _vp, _i32, _vp, _vp]),
     "nrng_ratio": (_i32, [_u64, _u64, _u64, _f64, _f64, _vp, _i32, _vp, _vp]),
     "nrng_polar_dev": (_i32, [_u64, _vp, _u64, _f64, _f64, _vp, _i32, _vp]),
+    "nrng_polar_noalloc": (_i32, [_u64, _u64, _u64, _f64, _f64, _vp, _i32, _vp, _vp]),
     "nrng_batched": (_i32, [_i32, _u32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _u64, _i32, _vp, _vp]),
     "nrng_batched_plan": (_i32, [_i32, _u32, _vp, _vp, _u64, _i32, _vp, _vp]),
     "nrng_batched_exec": (_i32, [_i32, _u32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp]),
@@ -176,6 +177,13 @@ def nrng_polar(seed, offset, n, mu, sigma, out, dtype, stream=None, d_consumed=N
     _need(d_consumed, 8, "nrng_polar d_consumed")
     _check("nrng_polar", lib().nrng_polar(seed & (2**64 - 1), offset & (2**64 - 1), n, mu, sigma, _ptr(out),
                                           dtype, _stream(stream), _ptr(d_consumed)))
+
+
+def nrng_polar_noalloc(seed, offset, n, mu, sigma, out, dtype, stream=None, d_consumed=None) -> None:
+    _need(out, n * _ESIZE.get(dtype, 0), "nrng_polar_noalloc out")
+    _need(d_consumed, 8, "nrng_polar_noalloc d_consumed")
+    _check("nrng_polar_noalloc", lib().nrng_polar_noalloc(seed & (2**64 - 1), offset & (2**64 - 1), n, mu, sigma,
+                                                          _ptr(out), dtype, _stream(stream), _ptr(d_consumed)))
 
 
 def nrng_polar2(seed, offset, n, mu, sigma, out, dtype, stream=None, d_consumed=None) -> None:

@@ -22,6 +22,8 @@ constexpr int kMaxDev = 64;
 struct DevState {
     bool init = false;
     int cus = 0;
+    // device address of the fixed scratch array (allocation-free entry point)
+    void *scratch = nullptr;
     // Polar workspace (see PolarArgs)
     uint64_t *masks = nullptr;
     uint64_t word_cap = 0;
@@ -86,8 +88,10 @@ bool capturing(hipStream_t s)
     return st != hipStreamCaptureStatusNone;
 }
 
-// Current device's state, initialised on first use.  Caller holds g_mu.
-int get_dev(DevState **out)
+// Current device's state without allocating: on first use the device is
+// queried and the address of the fixed scratch array taken (with the device
+// current).  Caller holds g_mu.
+int query_dev(DevState **out)
 {
     int dev = -1;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDev)
@@ -97,12 +101,30 @@ int get_dev(DevState **out)
         hipDeviceProp_t prop;
         if (hipGetDeviceProperties(&prop, dev) != hipSuccess)
             return NRNG_ENODEV;
+        void *sp = nullptr;
+        if (scratch_address(dev, &sp) != (int)hipSuccess || !sp)
+            return NRNG_EHIP;
         d.cus = prop.multiProcessorCount;
-        if (hipMalloc(&d.misc, 8 * sizeof(uint64_t)) != hipSuccess)
-            return NRNG_ENOMEM;
+        d.scratch = sp;
         d.init = true;
     }
     *out = &d;
+    return NRNG_OK;
+}
+
+// Current device's state with its base workspace (the cursor latch)
+// allocated.  Caller holds g_mu.
+int get_dev(DevState **out)
+{
+    DevState *d;
+    int rc = query_dev(&d);
+    if (rc)
+        return rc;
+    if (!d->misc && hipMalloc(&d->misc, 8 * sizeof(uint64_t)) != hipSuccess) {
+        d->misc = nullptr;
+        return NRNG_ENOMEM;
+    }
+    *out = d;
     return NRNG_OK;
 }
 
@@ -393,6 +415,27 @@ int polar_common(int vm, uint64_t seed, uint64_t offset, uint64_t *cursor, uint6
     return hip_status(launch_polar(MODE_SINGLE, vm, dtype, tu.vi, a, gm, gg, s));
 }
 
+// Layout of one single-stream Polar call in the fixed scratch array: byte
+// offsets of the masks (tiles x U words), tile prefixes, chunk totals, chunk
+// prefixes and the cursor latch, each 256-byte aligned.  False if they do
+// not fit kScratchBytes.
+struct ScratchLayout {
+    uint64_t masks, ipfx, csum, cpfx, misc, end;
+};
+
+bool scratch_layout(uint64_t tiles, uint64_t U, ScratchLayout *L)
+{
+    auto up = [](uint64_t x) { return (x + 255) / 256 * 256; };
+    const uint64_t chunks = tiles / kChunkTiles + 2;
+    L->masks = 0;
+    L->ipfx = up(L->masks + tiles * U * sizeof(uint64_t));
+    L->csum = up(L->ipfx + tiles * sizeof(uint32_t));
+    L->cpfx = up(L->csum + chunks * sizeof(uint32_t));
+    L->misc = up(L->cpfx + (chunks + 1) * sizeof(uint64_t));
+    L->end = L->misc + 8 * sizeof(uint64_t);
+    return L->end <= kScratchBytes;
+}
+
 // Trace and explicit-candidate hooks: masks go to the caller's buffer.
 int polar_hook(int mode, int vm, uint64_t seed, uint64_t offset, uint64_t ncand, const int32_t *xy,
                const uint64_t *uvw, double mu, double sigma, void *out, int dtype, uint64_t *masks,
@@ -544,6 +587,56 @@ int nrng_polar_dev(uint64_t seed, uint64_t *d_cursor, uint64_t n, double mu, dou
     if (!d_cursor)
         return NRNG_EINVAL;
     return polar_common(0, seed, 0, d_cursor, n, mu, sigma, out, dtype, S(stream), nullptr, 0);
+}
+
+int nrng_polar_noalloc(uint64_t seed, uint64_t offset, uint64_t n, double mu, double sigma, void *out, int dtype,
+                       void *stream, uint64_t *d_consumed)
+{
+    if (!dtype_ok(dtype))
+        return NRNG_EDTYPE;
+    int rc = check_mu_sigma(mu, sigma);
+    if (rc)
+        return rc;
+    if (n == 0)
+        return NRNG_OK;
+    if (!out)
+        return NRNG_EINVAL;
+    if (n > kScratchMaxN)
+        return NRNG_ERANGE;
+    std::lock_guard<std::mutex> lk(g_mu);
+    DevState *d;
+    if ((rc = query_dev(&d)))
+        return rc;
+    const Tune tu = g_tune[1][dtype];
+    const uint64_t U = polar_tile_words(tu.vi);
+    const uint64_t words = method_budget_words(NRNG_METHOD_POLAR, n);
+    const uint64_t tiles = (words + U - 1) / U;
+    ScratchLayout L;
+    if (!scratch_layout(tiles, U, &L))
+        return NRNG_ERANGE;
+    char *base = static_cast<char *>(d->scratch);
+    PolarArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.masks = reinterpret_cast<uint64_t *>(base + L.masks);
+    a.ipfx = reinterpret_cast<uint32_t *>(base + L.ipfx);
+    a.csum = reinterpret_cast<uint32_t *>(base + L.csum);
+    a.cpfx = reinterpret_cast<uint64_t *>(base + L.cpfx);
+    a.misc = reinterpret_cast<uint64_t *>(base + L.misc);
+    a.seed = seed;
+    a.offset = offset;
+    a.n = n;
+    a.nwords = words;
+    a.ntiles = tiles;
+    a.mu = mu;
+    a.sigma = sigma;
+    a.out = out;
+    a.consumed = d_consumed;
+    const uint64_t chunks = (tiles + kChunkTiles - 1) / kChunkTiles;
+    const uint32_t gm = persistent_grid(*d, polar_mask_blocks_per_cu(*d, MODE_SINGLE, 0, tu.vi), 0, chunks);
+    const uint64_t nw = polar_gen_waves(tu.vi);
+    const uint32_t gg = persistent_grid(*d, polar_blocks_per_cu(*d, MODE_SINGLE, 0, dtype, tu.vi), tu.grid_per_cu,
+                                        (tiles + nw - 1) / nw);
+    return hip_status(launch_polar(MODE_SINGLE, 0, dtype, tu.vi, a, gm, gg, S(stream)));
 }
 
 int nrng_test_polar_budget(uint64_t seed, uint64_t offset, uint64_t n, double mu, double sigma, void *out,

@@ -105,6 +105,14 @@ int launch_b1_batched(int bm, int dtype, int vi, const B1Args &a, uint32_t grid,
 int launch_polar(int mode, int vm, int dtype, int vi, const PolarArgs &a, uint32_t grid_mask, uint32_t grid_gen,
                  hipStream_t s, int part = 0);
 int launch_prep(const PrepArgs &a, hipStream_t s);
+
+// Fixed device scratch of the allocation-free Polar entry point: its size,
+// the largest n it serves, and its device address on device `dev` (which
+// must be the current device), taken once per device with
+// hipGetSymbolAddress and kept.  Returns a hipError_t as int.
+constexpr uint64_t kScratchBytes = 8ull << 20;
+constexpr uint64_t kScratchMaxN = 1ull << 26;
+int scratch_address(int dev, void **addr);
 int occupancy_polar(int mode, int vm, int dtype, int vi, int *blocks_per_cu);        // generate kernel
 int occupancy_polar_mask(int mode, int vm, int vi, int *blocks_per_cu);
 int occupancy_b1(int batched, int bm, int dtype, int vi, int *blocks_per_cu);

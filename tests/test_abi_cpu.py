@@ -73,6 +73,13 @@ def test_argument_errors_return_before_any_launch():
     assert L.nrng_ratio(1, 0, (1 << 41) + 1, 0.0, 1.0, p, 1, None, None) == nb.NRNG_ERANGE
     for fn in (L.nrng_boxmuller, L.nrng_b3, L.nrng_b2):
         assert fn(1, 0, (1 << 62) + 1, 0.0, 1.0, p, 1, None) == nb.NRNG_ERANGE
+    # the allocation-free Polar call serves at most 2^26 normals (its fixed
+    # scratch), and checks its arguments as nrng_polar does
+    assert L.nrng_polar_noalloc(1, 0, (1 << 26) + 1, 0.0, 1.0, p, 1, None, None) == nb.NRNG_ERANGE
+    assert L.nrng_polar_noalloc(1, 0, 10, 0.0, 1.0, p, 5, None, None) == nb.NRNG_EDTYPE
+    assert L.nrng_polar_noalloc(1, 0, 10, 0.0, -1.0, p, 1, None, None) == nb.NRNG_EINVAL
+    assert L.nrng_polar_noalloc(1, 0, 10, 0.0, 1.0, None, 1, None, None) == nb.NRNG_EINVAL
+    assert L.nrng_polar_noalloc(1, 0, 0, 0.0, 1.0, None, 1, None, None) == nb.NRNG_OK
     for m in range(6):
         assert L.nrng_batched(m, 4, p, p, p, None, p, p, p, (1 << 41) + 1, 1, None, None) == nb.NRNG_ERANGE
     # test hooks
