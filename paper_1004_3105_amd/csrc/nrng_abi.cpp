@@ -1,6 +1,6 @@
 // nrng_abi.cpp -- the C ABI of libnrng.so (declared in include/nrng.h):
 // argument validation, the per-device workspace, launch configuration and
-// dispatch to the kernels in nrng_kernels.hip.
+// dispatch to the kernels (nrng_kernels_*.hip).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -143,11 +143,12 @@ int ensure_polar_ws(DevState &d, uint64_t tiles, uint64_t words, hipStream_t s)
     const uint64_t chunks = tcap / kChunkTiles + 2;
     if (hipDeviceSynchronize() != hipSuccess)
         return NRNG_EHIP;
-    hipFree(d.masks);
-    hipFree(d.ipfx);
-    hipFree(d.tile_stream);
-    hipFree(d.csum);
-    hipFree(d.cpfx);
+    // freeing is best effort: the pointers are dropped either way
+    (void)hipFree(d.masks);
+    (void)hipFree(d.ipfx);
+    (void)hipFree(d.tile_stream);
+    (void)hipFree(d.csum);
+    (void)hipFree(d.cpfx);
     d.masks = nullptr;
     d.ipfx = nullptr;
     d.tile_stream = nullptr;
@@ -176,7 +177,7 @@ int ensure_streams(DevState &d, uint64_t nstreams, hipStream_t s)
         return NRNG_EHIP;
     for (uint64_t **p : {&d.tile_start, &d.stream_words, &d.packed_off}) {
         if (*p)
-            hipFree(*p);
+            (void)hipFree(*p);
         *p = nullptr;
     }
     d.stream_cap = 0;
@@ -851,13 +852,13 @@ int nrng_fillgraph_create(uint64_t seed, uint64_t *d_cursor, uint64_t n, double 
     const hipError_t e = hipStreamEndCapture(s, &gr);
     if (rc || e != hipSuccess || !gr) {
         if (gr)
-            hipGraphDestroy(gr);
+            (void)hipGraphDestroy(gr);
         delete g;
         return rc ? rc : NRNG_EHIP;
     }
     g->graph = gr;
     if (hipGraphInstantiate(&g->exec, gr, nullptr, nullptr, 0) != hipSuccess) {
-        hipGraphDestroy(gr);
+        (void)hipGraphDestroy(gr);
         delete g;
         return NRNG_EHIP;
     }
@@ -878,10 +879,10 @@ int nrng_fillgraph_destroy(void *graph)
     if (!graph)
         return NRNG_OK;
     FillGraph *g = static_cast<FillGraph *>(graph);
-    hipGraphExecDestroy(g->exec);
-    hipGraphDestroy(g->graph);
+    const bool ok = hipGraphExecDestroy(g->exec) == hipSuccess;
+    const bool ok2 = hipGraphDestroy(g->graph) == hipSuccess;
     delete g;
-    return NRNG_OK;
+    return ok && ok2 ? NRNG_OK : NRNG_EHIP;
 }
 
 // Index of the compiled variant (wg, unroll) of a kernel, or -1.

@@ -53,6 +53,62 @@ __device__ __forceinline__ uint64_t splitmix64_mix(uint64_t z)
     return z ^ (z >> 31);
 }
 
+// Runs of counters whose z = c + kGamma share one high word zh (a tile of
+// consecutive counters that does not cross a multiple of 2^32 in z; the
+// caller checks this once per tile).  With z = zh 2^32 + zl, the first
+// round's high half z1h = zh ^ (zh >> 30) and its contribution z1h * C1lo
+// to the high word of the first product depend on zh alone, so they are
+// formed once per run (in scalar registers when zh is wave-uniform).  Per
+// counter the first round then costs a funnel shift and an xor for the low
+// half and one 32 x 32 -> 64-bit multiply-add plus a multiply-add on the
+// high word for the product, against a 64-bit shift, two xors and four
+// multiply instructions in the general form.  The result is SplitMix64's,
+// bit for bit.
+struct SmRun {
+    uint32_t zh;     // high word of z, common to the run
+    uint32_t k1;     // low word of (zh ^ (zh >> 30)) * 0x1CE4E5B9
+};
+
+__device__ __forceinline__ SmRun sm_run(uint64_t z_any_in_run)
+{
+    SmRun r;
+    r.zh = (uint32_t)(z_any_in_run >> 32);
+    r.k1 = (r.zh ^ (r.zh >> 30)) * 0x1CE4E5B9u;
+    return r;
+}
+
+// (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9 mod 2^64 for z = (r.zh, zl).
+__device__ __forceinline__ uint64_t sm_round1(const SmRun &r, uint32_t zl)
+{
+    const uint32_t z1l = zl ^ __builtin_amdgcn_alignbit(r.zh, zl, 30);
+    const uint64_t m = (uint64_t)z1l * 0x1CE4E5B9u;
+    const uint32_t ph = (uint32_t)(m >> 32) + z1l * 0xBF58476Du + r.k1;
+    return ((uint64_t)ph << 32) | (uint32_t)m;
+}
+
+// Top 32 bits of the hash, as splitmix64_mix_hi.
+__device__ __forceinline__ uint32_t sm_hi(const SmRun &r, uint32_t zl)
+{
+    uint64_t z = sm_round1(r, zl);
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    const uint32_t h = (uint32_t)(z >> 32);
+    return h ^ (h >> 31);
+}
+
+// The full hash, as splitmix64_mix.
+__device__ __forceinline__ uint64_t sm_full(const SmRun &r, uint32_t zl)
+{
+    uint64_t z = sm_round1(r, zl);
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// True when every z in [zb, zb + span) has the high word of zb (span >= 1).
+__device__ __forceinline__ bool sm_run_fits(uint64_t zb, uint64_t span)
+{
+    return (uint64_t)(uint32_t)zb + (span - 1) <= 0xFFFFFFFFull;
+}
+
 // ---------------------------------------------------------------------------
 // Output element types.  OutT is the storage type; the arithmetic is FP64 for
 // double output (the plain FP64 kernels) and FP32 otherwise.
@@ -313,6 +369,37 @@ __device__ __forceinline__ uint64_t polar_S(int32_t X, int32_t Y)
 __device__ __forceinline__ bool polar_accept(uint64_t S)
 {
     return S - 1 < (1ull << 62) - 1;
+}
+
+// The same test from X and Y: S - 1 = X^2 + (Y^2 - 1) by two signed
+// 32 x 32 -> 64-bit multiply-adds (the -1 rides in the first one's addend;
+// S = 0 gives 2^64 - 1, rejected), then the unsigned comparison.
+// Y^2 - 1 as one v_mad_i64_i32 with the addend -1 (written as the
+// instruction: the compiler otherwise reassociates (X^2 + (Y^2 - 1)) into
+// (X^2 + Y^2) - 1 and spends a 64-bit add on the -1).
+__device__ __forceinline__ int64_t sq_minus_one(int32_t y)
+{
+    int64_t r;
+    uint64_t carry;
+    asm("v_mad_i64_i32 %0, %1, %2, %2, -1" : "=v"(r), "=s"(carry) : "v"(y));
+    return r;
+}
+
+__device__ __forceinline__ bool polar_accept_xy(int32_t X, int32_t Y)
+{
+    const uint64_t sm1 = (uint64_t)((int64_t)X * (int64_t)X + sq_minus_one(Y));
+    return sm1 < (1ull << 62) - 1;
+}
+
+// 2 piece + (bit `lane` of m): one v_addc with the lane mask m as its carry
+// in (the compiler otherwise forms the bit by a select and merges it with a
+// shift and an or).
+__device__ __forceinline__ uint32_t shift_in(uint32_t piece, uint64_t m)
+{
+    uint32_t r;
+    uint64_t carry;
+    asm("v_addc_co_u32_e64 %0, %1, %2, %2, %3" : "=v"(r), "=s"(carry) : "v"(piece), "s"(m));
+    return r;
 }
 
 // FP64 value: s = RNE(S) 2^-62, r = sigma sqrt(-2 ln(s) / s), no fused

@@ -1,5 +1,5 @@
 // nrng_launch.hpp -- internal interface between the C ABI (nrng_abi.cpp) and
-// the kernels (nrng_kernels.hip).  Not installed.
+// the kernels (nrng_kernels_*.hip).  Not installed.
 #pragma once
 
 #include <hip/hip_runtime.h>
