@@ -9,8 +9,9 @@ kernel, through the C ABI.  The printed `value` is the whole step's
 throughput in normals per second (both methods' normals over the step time),
 with every input resident in GPU memory before timing starts.
 
-Alongside, outside the timed region: the measured store-only and hash-only
-ceilings, the single-stream fills of 2^30 normals (FP32, BF16, FP16 and the
+Alongside, outside the timed region: the measured store-only ceiling (best
+of a sweep over plain and nontemporal stores and launch shapes), the
+hash-only ceiling, the single-stream fills of 2^30 normals (FP32, BF16, FP16 and the
 plain FP64 kernels, the comparison point of the FP32 batched figure), the
 graph-replayed repeated fill (64 x 2^28 Polar normals), methods P2 (Section
 4), B3 and B2 (Section 3) and Algorithm R (Section 5) on the same batched
@@ -38,62 +39,68 @@ HBM_PEAK_GBS = 8000.0          # MI355X datasheet HBM3E bandwidth
 # as 2 flops on 2 packed values: 157.3 / 4)
 VALU_PEAK_TOPS = 39.32
 # Algorithmic VALU lane operations per unit of work of each kernel: the
-# 32-bit VALU operations the method's arithmetic needs, counted step by step
-# (64-bit add 1, 64-bit shift 1, 64-bit xor 2, 64 x 64 -> 64 multiply 4,
-# high word of a 64 x 64 multiply 4, conversions, compares, selects, FMAs and
-# each transcendental 1).  SplitMix64: full 18, top word only 17.
-#   polar_count:    per candidate: 2 hashes (top words) 34 + X^2 + Y^2 2 +
-#                   0 < S < 2^62 test 2
-#   polar_generate: per pair: 2 hashes 34 + S 2 + the FP32 radius with the
-#                   exact complement near s = 1 (complement and select 5,
-#                   conversion 4, remainder and selects 7, log and
-#                   reciprocal square root 2, scalings 4) 22 + 2 conversions
-#                   and 2 FMAs 4
-#   b1_batched:     per pair: hash of u 18 + hash of v (top word) 17 +
+# 32-bit VALU operations of the method's own arithmetic, counted step by
+# step in its cheapest form here.  A SplitMix64 hash of a counter inside a
+# tile whose counters share the high word of z = c + gamma costs 15 (top
+# word: counter add 1, first round on the low word 2, first product 3,
+# second round's 64-bit shift and two xors 3, top word of the second product
+# 4, final shift and xor 2) or 17 (full hash: the whole second product 4 and
+# the final 64-bit xor-shift 4).  A kernel's re-computation of work another
+# kernel already did (the generate kernels' second hash of each accepted
+# candidate) is not the method's work: it is listed in IMPL_OVERHEAD.
+#   polar_count:    per candidate: 2 top-word hashes 30 + S - 1 = X^2 + (Y^2 - 1)
+#                   by two multiply-adds 2 + the unsigned test 1
+#   polar_generate: per pair: the FP32 radius with the exact complement near
+#                   s = 1 (complement and select 5, conversion 4, remainder
+#                   and selects 7, log and reciprocal square root 2,
+#                   scalings 4) 22 + 2 conversions and 2 FMAs 4
+#   b1_batched:     per pair: full hash of u 17 + top-word hash of v 15 +
 #                   ln(1 - u) with the exact complement 21 + angle reduction,
 #                   conversion, sin, cos 9 + 2 FMAs
-#   p2_count:       per candidate: as polar_count with the one-sided test
-#                   S < 2^62 (1)
-#   p2_generate:    per pair: 2 hashes 34 + S 2 + s from the top word 1 +
-#                   v = (6s - 4)/(4 - 3s) 4 + degree-9 Horner 9 + split test
-#                   and select 2 + the library branch for s > 8/9 (10
-#                   operations, taken by 1/9 of the pairs) 1 + scaling 1 +
-#                   2 conversions and 2 FMAs 4
-#   b3_batched:     per pair: hashes of u1 and u2 (18 each) and of u3 (top
-#                   word, 17) + m = max 3 + conversion 3 + u = m^2 1 + v 4 +
+#   p2_count:       per candidate: as polar_count, the one-sided test S < 2^62
+#   p2_generate:    per pair: s from the top word 1 + v = (6s - 4)/(4 - 3s) 4 +
+#                   degree-9 Horner 9 + split test and select 2 + the library
+#                   branch for s > 8/9 (10 operations, taken by 1/9 of the
+#                   pairs) 1 + scaling 1 + 2 conversions and 2 FMAs 4
+#   b3_batched:     per pair: full hashes of u1 and u2 (17 each) and the top
+#                   word of u3 (15) + m = max 3 + conversion 3 + u = m^2 1 + v 4 +
 #                   degree-9 Horner 9 + scaling 2 + the library branch's 9
 #                   operations for the 1/9 of pairs above 8/9 1 + split test and
 #                   select 2 + angle reduction, conversion, sin, cos 8 + 2 FMAs
-#   ratio_count:    per candidate: 2 hashes 36 + v - 1/2 and 1 - u as
+#   ratio_count:    per candidate: 2 full hashes 34 + v - 1/2 and 1 - u as
 #                   integers 4 + their conversions (signed split 5, unsigned
 #                   3) 8 + x = c dv / du 3 + x^2 1 + -4 ln(1 - u) (scale, log,
 #                   scale) 3 + the comparison 1 + the FP32 screening band
 #                   (difference, sum, FMA, compare) 4; the FP64 test inside
 #                   the band (under 1e-4 of candidates) 0
-#   ratio_generate: per output: 2 hashes 36 + the integer differences 4 +
-#                   conversions 8 + x 3 + 1 FMA
-#   b2_batched:     per pair: hash of u 18 + hash of v (top word) 17 +
+#   ratio_generate: per output: the integer differences 4 + conversions 8 +
+#                   x 3 + 1 FMA
+#   b2_batched:     per pair: full hash of u 17 + top-word hash of v 15 +
 #                   ln(1 - u) with the exact complement 21 + quarter-turn
 #                   reduction, conversion and scaling of y 6 + t = y^2 and
 #                   the two polynomials (6 FMAs, 1 product) 8 + four
 #                   doublings (d = 2s, s' = d c, c' = 1 - d s) 12 + 2 FMAs
-ALU_OPS = {"polar_count": 38, "polar_generate": 62, "b1_batched": 67, "p2_count": 37, "p2_generate": 58,
-           "b3_batched": 88, "ratio_count": 60, "ratio_generate": 52, "b2_batched": 84}
+ALU_OPS = {"polar_count": 33, "polar_generate": 26, "b1_batched": 64, "p2_count": 33, "p2_generate": 22,
+           "b3_batched": 84, "ratio_count": 58, "ratio_generate": 16, "b2_batched": 81}
+# What the generate kernels compute again per unit, beyond the method's own
+# work: the two hashes of the accepted candidate and S (P, P2: 2 x 15 + 2),
+# the two full hashes (R: 2 x 17).
+IMPL_OVERHEAD = {"polar_generate": 32, "p2_generate": 32, "ratio_generate": 34}
 # The same counts by instruction class, for weighting by the measured issue
-# cost of each class (extras "valu_issue_cost"): 32-bit multiplies and 64-bit
-# multiply-adds (a hash has 6), 64-bit shifts (2 in a top-word hash, 3 in a
-# full one), 64-bit adds (the counter step), transcendentals (log, sqrt, rcp,
-# rsq, sin, cos), and the rest (FMA-like, cost 1).
+# cost of each class (extras "valu_issue_cost"): 32-bit multiplies and
+# 32 x 32 -> 64-bit multiply-adds (5 in a hash), 64-bit shifts (1 in a
+# hash), 64-bit adds, transcendentals (log, sqrt, rcp, rsq, sin, cos), and
+# the rest (FMA-like, cost 1).
 ALU_MIX = {
-    "polar_count": {"mul": 14, "shr64": 4, "add64": 2, "trans": 0, "other": 18},
-    "polar_generate": {"mul": 14, "shr64": 4, "add64": 2, "trans": 2, "other": 40},
-    "b1_batched": {"mul": 12, "shr64": 5, "add64": 2, "trans": 4, "other": 44},
-    "p2_count": {"mul": 14, "shr64": 4, "add64": 2, "trans": 0, "other": 17},
-    "p2_generate": {"mul": 14, "shr64": 4, "add64": 2, "trans": 1, "other": 37},
-    "b3_batched": {"mul": 18, "shr64": 8, "add64": 3, "trans": 3, "other": 56},
-    "ratio_count": {"mul": 12, "shr64": 6, "add64": 2, "trans": 2, "other": 38},
-    "ratio_generate": {"mul": 12, "shr64": 6, "add64": 2, "trans": 1, "other": 31},
-    "b2_batched": {"mul": 12, "shr64": 5, "add64": 2, "trans": 2, "other": 63},
+    "polar_count": {"mul": 12, "shr64": 2, "add64": 0, "trans": 0, "other": 19},
+    "polar_generate": {"mul": 0, "shr64": 0, "add64": 1, "trans": 2, "other": 23},
+    "b1_batched": {"mul": 10, "shr64": 2, "add64": 1, "trans": 4, "other": 47},
+    "p2_count": {"mul": 12, "shr64": 2, "add64": 0, "trans": 0, "other": 19},
+    "p2_generate": {"mul": 0, "shr64": 0, "add64": 0, "trans": 1, "other": 21},
+    "b3_batched": {"mul": 15, "shr64": 3, "add64": 0, "trans": 3, "other": 63},
+    "ratio_count": {"mul": 10, "shr64": 2, "add64": 0, "trans": 2, "other": 44},
+    "ratio_generate": {"mul": 0, "shr64": 0, "add64": 0, "trans": 1, "other": 15},
+    "b2_batched": {"mul": 10, "shr64": 2, "add64": 1, "trans": 2, "other": 66},
 }
 ALU_UNIT = {"polar_count": "candidate", "polar_generate": "output pair", "b1_batched": "output pair",
             "p2_count": "candidate", "p2_generate": "output pair", "b3_batched": "output pair",
@@ -140,6 +147,26 @@ def read_traffic(kernel_tag: str):
         return None
     try:
         return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def read_profile_avg(kernel_tag: str):
+    """The average duration (ms) of this kernel in the committed rocprofv3
+    kernel-trace summary, if it was taken on the current kernel source."""
+    path = os.path.join(PROFILES, "avg_%s.txt" % kernel_tag)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as f:
+        for line in f:
+            if "=" in line and not line.startswith("#"):
+                k, v = line.split("=", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("source_hash") != kernel_source_hash():
+        return None
+    try:
+        return float(kv["avg_ms"])
     except (KeyError, ValueError):
         return None
 
@@ -258,7 +285,10 @@ def main() -> int:
         plan_ms, count_ms = avg(bd_events, 0, 1), avg(bd_events, 1, 2)
         exec_ms = count_ms + gen_ms
         gbs = 4.0 * total / (exec_ms * 1e-3) / 1e9
+        kid = nb.KERNEL_B1_BATCHED if name in ("b1", "b3", "b2") else nb.KERNEL_POLAR
+        wg, un, gpc = nb.nrng_tune_get(kid, nb.NRNG_F32)
         per_kernel[name] = {"plan_ms": round(plan_ms, 5), "exec_ms": round(exec_ms, 5),
+                            "variant": {"wg": wg, "unroll": un, "grid_per_cu": gpc},
                             "normals_per_s": total / (exec_ms * 1e-3), "write_GBps": round(gbs, 1),
                             "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)}
         if name in ("polar", "p2", "ratio"):
@@ -275,18 +305,36 @@ def main() -> int:
             per_kernel[name].setdefault("alu", {})[k] = {
                 "ms": round(ms, 5), "Tops_per_s": round(ops / (ms * 1e-3) / 1e12, 2),
                 "frac_valu_peak": round(ops / (ms * 1e-3) / 1e12 / VALU_PEAK_TOPS, 4)}
+        if name in ("polar", "p2", "ratio"):
+            # the method as a whole (count + generate) on its own operations,
+            # and the generate kernel's re-computation beside it
+            ops = sum(ALU_OPS[k] * (cand if k.endswith("_count") else gen_units) for k in units)
+            per_kernel[name]["alu_method"] = {
+                "ms": round(exec_ms, 5), "ops": ops,
+                "frac_valu_peak": round(ops / (exec_ms * 1e-3) / 1e12 / VALU_PEAK_TOPS, 4),
+                "generate_recomputed_ops_per_unit": IMPL_OVERHEAD[name + "_generate"]}
 
-    # dominant kernel -> roofline (ALU-bound: VALU lane operations)
-    # (among the part-2 kernels, whose durations come from the timed steps)
+    # dominant kernel -> roofline (ALU-bound: VALU lane operations on the
+    # method's own work), with its HBM write rate beside (bytes: the output
+    # only, 4 B per FP32 normal) (among the part-2 kernels, whose durations
+    # come from the timed steps)
     kern = {k: v for pk in per_kernel.values() for k, v in pk["alu"].items() if not k.endswith("_count")}
     dom = max(kern, key=lambda k: kern[k]["ms"])
     traffic = read_traffic("batched_%s_f32" % dom)
+    wbytes = 4 * total
     roofline = {"bound": "alu", "achieved": kern[dom]["Tops_per_s"], "peak": VALU_PEAK_TOPS,
                 "unit": "Tlane-op/s", "frac": kern[dom]["frac_valu_peak"], "traffic": traffic,
                 "kernel": KERNEL_NAMES[dom], "ms_per_launch": kern[dom]["ms"],
                 "ops_per_unit": ALU_OPS[dom], "unit_of_work": ALU_UNIT[dom],
                 "timed_by": "HIP events around this kernel in every timed step, on its launch stream",
-                "algorithmic_write_bytes_per_launch": 4 * total}
+                "algorithmic_write_bytes_per_launch": wbytes,
+                "hbm": {"achieved_GBps": round(wbytes / (kern[dom]["ms"] * 1e-3) / 1e9, 1), "peak_GBps": HBM_PEAK_GBS,
+                        "frac": round(wbytes / (kern[dom]["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}}
+    if dom in IMPL_OVERHEAD:
+        roofline["recomputed_ops_per_unit"] = IMPL_OVERHEAD[dom]
+    prof = read_profile_avg("batched_%s_f32" % dom)
+    if prof is not None:
+        roofline["rocprof_avg_ms"] = prof
 
     result = {
         "metric": METRIC,
@@ -305,7 +353,9 @@ def main() -> int:
                    "batched %d streams, %s only, FP32 out" % (ns, methods[0][0]),
                    "nstreams": ns, "normals_per_method": total,
                    "lengths": "log-uniform on [1e2, 1e6]", "mu": "U(-10, 10)", "sigma": "U(0.1, 5)",
-                   "seed_source": "PCG64(0xBA7C4)", "parallelism": "single GPU"},
+                   "seed_source": "PCG64(0xBA7C4)",
+                   "seed_note": "per-stream lengths, mu, sigma and 64-bit seeds are drawn from PCG64 seeded "
+                                "0xBA7C4, not seed_j = hash(j)", "parallelism": "single GPU"},
         "hbm_write_frac": round(4.0 * normals / elapsed / 1e9 / HBM_PEAK_GBS, 4),
         "kernels": per_kernel,
         "roofline": roofline,
@@ -420,11 +470,20 @@ def extras(nb, torch, dev, stream, per_kernel, batched_value):
             ts.append(a.elapsed_time(b))
         return median(ts)
 
-    # store-only and hash-only ceilings
+    # store-only ceiling: the best of plain and nontemporal 16-byte stores
+    # over workgroups per CU and stores per thread per step (4 GiB each)
     nbytes = 4 << 30
     buf = torch.empty(nbytes // 4, dtype=torch.float32, device=dev)
-    ms = timed(lambda: nb.nrng_probe_store(buf, nbytes, stream), 10)
-    ex["store_ceiling_GBps"] = round(nbytes / (ms * 1e-3) / 1e9, 1)
+    sweep = {}
+    for nt in (0, 1):
+        for bpc in (4, 8, 16, 32):
+            for unr in (1, 2, 4, 8):
+                ms = timed(lambda: nb.nrng_probe_store_variant(buf, nbytes, nt, bpc, unr, stream), 4)
+                sweep["%s_wg%d_u%d" % ("nt" if nt else "plain", bpc, unr)] = round(nbytes / (ms * 1e-3) / 1e9, 1)
+    best = max(sweep, key=sweep.get)
+    ex["store_ceiling_GBps"] = sweep[best]
+    ex["store_ceiling_form"] = best
+    ex["store_sweep_GBps"] = sweep
     sink = torch.empty(256 * 2048, dtype=torch.int64, device=dev)
     nh = 1 << 33
     ms = timed(lambda: nb.nrng_probe_hash(1, nh, sink, sink.numel(), stream), 5)
@@ -508,7 +567,7 @@ def cpu_baseline(cfg, methods):
 
     import oracle as O
     O.lib()
-    cores = min(16, os.cpu_count() or 1)
+    cores = os.cpu_count() or 1   # every host core the process sees (nproc)
     ns = len(cfg["n"])
     jobs = [(m, j) for m in methods for j in range(ns)]
 
@@ -529,7 +588,11 @@ def cpu_baseline(cfg, methods):
         t1 = time.perf_counter()
         fn(seed, 0, n)
         single[key + "_normals_per_s"] = n / (time.perf_counter() - t1)
-    return {"value": done / dt, "unit": "normals/s", "cores": cores, "kind": "oracle",
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        affinity = cores
+    return {"value": done / dt, "unit": "normals/s", "cores": cores, "nproc_affinity": affinity, "kind": "oracle",
             "sample": "the whole batched workload: %d streams x %s, %d normals, one FP64 oracle call per "
                       "stream on a %d-thread pool (%.1f s wall)" % (ns, "+".join(methods), done, cores, dt),
             "single_thread": single}

@@ -405,6 +405,15 @@ int nrng_test_ratio_budget(uint64_t seed, uint64_t offset, uint64_t n, double mu
  *   into d_sink[0..gridsize) -- the hash-only VALU ceiling.
  * ---------------------------------------------------------------------- */
 int nrng_probe_store(void *out, uint64_t nbytes, void *stream);
+/* nrng_probe_store_variant: the store-only ceiling in a chosen form:
+ *   nontemporal != 0 writes with nontemporal 16-byte stores
+ *   (global_store_dwordx4 ... nt), else plain ones; blocks_per_cu
+ *   workgroups of 256 threads per compute unit (1 to 32); unroll 16-byte
+ *   stores per thread per step (1, 2, 4 or 8), each wave store writing
+ *   1 KiB contiguously.  NRNG_EINVAL for other values or nbytes not a
+ *   multiple of 16. */
+int nrng_probe_store_variant(void *out, uint64_t nbytes, int nontemporal, uint32_t blocks_per_cu, uint32_t unroll,
+                             void *stream);
 int nrng_probe_copy(void *dst, const void *src, uint64_t nbytes, void *stream);
 int nrng_probe_hash(uint64_t seed, uint64_t nhash, uint64_t *d_sink, uint64_t sink_len, void *stream);
 

@@ -61,6 +61,7 @@ _SIGS = {
     "nrng_test_ratio_budget": (_i32, [_u64, _u64, _u64, _f64, _f64, _vp, _i32, _u32, _vp, _vp]),
     "nrng_probe_store": (_i32, [_vp, _u64, _vp]),
     "nrng_probe_copy": (_i32, [_vp, _vp, _u64, _vp]),
+    "nrng_probe_store_variant": (_i32, [_vp, _u64, _i32, _u32, _u32, _vp]),
     "nrng_probe_hash": (_i32, [_u64, _u64, _vp, _u64, _vp]),
     "nrng_probe_valu": (_i32, [_i32, ctypes.c_uint32, _vp, _u64, _vp]),
     "nrng_tune_load": (_i32, [ctypes.c_char_p]),
@@ -363,6 +364,12 @@ def nrng_test_ratio_budget(seed, offset, n, mu, sigma, out, dtype, words, stream
 def nrng_probe_store(out, nbytes, stream=None) -> None:
     _need(out, nbytes, "nrng_probe_store out")
     _check("nrng_probe_store", lib().nrng_probe_store(_ptr(out), nbytes, _stream(stream)))
+
+
+def nrng_probe_store_variant(out, nbytes, nontemporal, blocks_per_cu, unroll, stream=None) -> None:
+    _need(out, nbytes, "nrng_probe_store_variant out")
+    _check("nrng_probe_store_variant", lib().nrng_probe_store_variant(_ptr(out), nbytes, int(nontemporal),
+                                                                      blocks_per_cu, unroll, _stream(stream)))
 
 
 def nrng_probe_copy(dst, src, nbytes, stream=None) -> None:

@@ -54,14 +54,15 @@ struct Tune {
 
 std::mutex g_mu;
 DevState g_dev[kMaxDev];
-// Defaults chosen by the autotuner on MI355X (paper_1004_3105_amd/autotune.py,
-// table tune_gfx950.json); [kernel][dtype], kernel ids: 0 = B1 single,
-// 1 = Polar, 2 = B1 batched; dtype order F64, F32, BF16, F16; entries are
-// {variant index, grid cap per CU (0 = occupancy)}.
+// Defaults: the table paper_1004_3105_amd/tune_gfx950.txt that the
+// autotuner (paper_1004_3105_amd/autotune.py) wrote on MI355X for the
+// current kernels.  [kernel][dtype], kernel ids: 0 = B1 single, 1 = Polar,
+// 2 = B1 batched; dtype order F64, F32, BF16, F16; entries are {variant
+// index, grid cap per CU (0 = occupancy)}.
 Tune g_tune[3][4] = {
-    {{4, 0}, {1, 0}, {4, 0}, {4, 0}},
-    {{2, 4}, {1, 0}, {3, 4}, {3, 0}},
-    {{2, 4}, {4, 0}, {4, 0}, {1, 0}},
+    {{4, 0}, {2, 0}, {3, 0}, {4, 0}},
+    {{1, 0}, {1, 0}, {1, 0}, {1, 0}},
+    {{2, 4}, {4, 0}, {4, 0}, {2, 0}},
 };
 
 inline hipStream_t S(void *s) { return reinterpret_cast<hipStream_t>(s); }
@@ -1090,6 +1091,25 @@ int nrng_probe_store(void *out, uint64_t nbytes, void *stream)
             return rc;
     }
     return hip_status(launch_probe_store(out, nbytes, (uint32_t)d->cus * 32, S(stream)));
+}
+
+int nrng_probe_store_variant(void *out, uint64_t nbytes, int nontemporal, uint32_t blocks_per_cu, uint32_t unroll,
+                             void *stream)
+{
+    if (!out || nbytes % 16 || blocks_per_cu < 1 || blocks_per_cu > 32 ||
+        !(unroll == 1 || unroll == 2 || unroll == 4 || unroll == 8))
+        return NRNG_EINVAL;
+    if (nbytes == 0)
+        return NRNG_OK;
+    DevState *d;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        int rc = get_dev(&d);
+        if (rc)
+            return rc;
+    }
+    return hip_status(launch_probe_store_var(out, nbytes, nontemporal != 0, unroll, (uint32_t)d->cus * blocks_per_cu,
+                                             S(stream)));
 }
 
 int nrng_probe_copy(void *dst, const void *src, uint64_t nbytes, void *stream)

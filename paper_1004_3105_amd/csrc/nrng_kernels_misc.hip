@@ -170,6 +170,30 @@ __global__ __launch_bounds__(256) void probe_store_kernel(uint4 *out, uint64_t n
         out[i] = make_uint4(0x3F800000u, 0x40000000u, 0x40400000u, (uint32_t)i);
 }
 
+// The store-only ceiling in a chosen form: UNR 16-byte stores per thread
+// per step, each thread's stores 256 x 16 bytes apart (so that every store
+// instruction of a wave writes 1 KiB contiguously), plain or nontemporal.
+template <bool NT, int UNR>
+__global__ __launch_bounds__(256) void probe_store_var_kernel(uint4 *out, uint64_t n16)
+{
+    const uint64_t step = (uint64_t)gridDim.x * 256 * UNR;
+    for (uint64_t base = blockIdx.x * 256ull * UNR + threadIdx.x; base < n16; base += step) {
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            const uint64_t i = base + (uint64_t)u * 256;
+            if (i < n16) {
+                typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+                const u4 v = {0x3F800000u, 0x40000000u, 0x40400000u, (uint32_t)i};
+                u4 *q = reinterpret_cast<u4 *>(out + i);
+                if constexpr (NT)
+                    __builtin_nontemporal_store(v, q);
+                else
+                    *q = v;
+            }
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void probe_copy_kernel(uint4 *dst, const uint4 *src, uint64_t n16)
 {
     const uint64_t stride = (uint64_t)gridDim.x * 256;
@@ -333,6 +357,27 @@ int launch_probe_store(void *out, uint64_t nbytes, uint32_t grid, hipStream_t s)
 {
     hipLaunchKernelGGL(probe_store_kernel, dim3(grid), dim3(256), 0, s, (uint4 *)out, nbytes / 16);
     return (int)hipGetLastError();
+}
+
+int launch_probe_store_var(void *out, uint64_t nbytes, int nt, uint32_t unroll, uint32_t grid, hipStream_t s)
+{
+    const void *fn = nullptr;
+    switch (unroll * 2 + (nt ? 1 : 0)) {
+    case 2: fn = (const void *)probe_store_var_kernel<false, 1>; break;
+    case 3: fn = (const void *)probe_store_var_kernel<true, 1>; break;
+    case 4: fn = (const void *)probe_store_var_kernel<false, 2>; break;
+    case 5: fn = (const void *)probe_store_var_kernel<true, 2>; break;
+    case 8: fn = (const void *)probe_store_var_kernel<false, 4>; break;
+    case 9: fn = (const void *)probe_store_var_kernel<true, 4>; break;
+    case 16: fn = (const void *)probe_store_var_kernel<false, 8>; break;
+    case 17: fn = (const void *)probe_store_var_kernel<true, 8>; break;
+    }
+    if (!fn)
+        return (int)hipErrorInvalidValue;
+    uint4 *o = (uint4 *)out;
+    uint64_t n16 = nbytes / 16;
+    void *args[] = {&o, &n16};
+    return (int)hipLaunchKernel(fn, dim3(grid), dim3(256), args, 0, s);
 }
 
 int launch_probe_copy(void *dst, const void *src, uint64_t nbytes, uint32_t grid, hipStream_t s)

@@ -117,6 +117,7 @@ int occupancy_polar(int mode, int vm, int dtype, int vi, int *blocks_per_cu);   
 int occupancy_polar_mask(int mode, int vm, int vi, int *blocks_per_cu);
 int occupancy_b1(int batched, int bm, int dtype, int vi, int *blocks_per_cu);
 int launch_probe_store(void *out, uint64_t nbytes, uint32_t grid, hipStream_t s);
+int launch_probe_store_var(void *out, uint64_t nbytes, int nt, uint32_t unroll, uint32_t grid, hipStream_t s);
 int launch_probe_copy(void *dst, const void *src, uint64_t nbytes, uint32_t grid, hipStream_t s);
 constexpr int kProbeValuOps = 15;   // instructions of the issue-rate probe (see nrng.h)
 int launch_probe_valu(int op, uint32_t iters, uint32_t *sink, uint64_t sink_len, uint32_t grid, hipStream_t s);

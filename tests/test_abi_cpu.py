@@ -195,3 +195,15 @@ def test_tune_load_applies_a_valid_table_and_rejects_a_bad_one(tmp_path):
     finally:
         for (k, d), v in saved.items():
             nb.nrng_tune_set(k, d, *v)
+
+
+def test_compiled_defaults_equal_the_committed_tune_table():
+    """The library's compiled launch defaults are the table the autotuner
+    wrote for the current kernels (paper_1004_3105_amd/tune_gfx950.txt)."""
+    path = os.path.join(ROOT, "paper_1004_3105_amd", "tune_gfx950.txt")
+    kid = {"b1": nb.KERNEL_B1, "polar": nb.KERNEL_POLAR, "b1_batched": nb.KERNEL_B1_BATCHED}
+    did = {"f64": nb.NRNG_F64, "f32": nb.NRNG_F32, "bf16": nb.NRNG_BF16, "f16": nb.NRNG_F16}
+    rows = [l.split() for l in open(path) if l.strip() and not l.startswith("#")]
+    assert len(rows) == 12
+    for k, d, wg, un, gpc in rows:
+        assert nb.nrng_tune_get(kid[k], did[d]) == (int(wg), int(un), int(gpc)), (k, d)
