@@ -532,6 +532,21 @@ def extras(nb, torch, dev, stream, per_kernel, batched_value):
         "step_vs_mean_fp64": batched_value / (0.5 * (f64["b1_normals_per_s"] + f64["polar_normals_per_s"])),
     }
 
+    # the two small parity configurations: B1 FP64 2^20 normals (seed 1) and
+    # Polar 2^24 normals (seed 7), FP64 and FP32
+    small = {}
+    for key, fn, seed, n, dt, el in (("b1_f64_2^20", nb.nrng_boxmuller, 1, 1 << 20, nb.NRNG_F64, 8),
+                                     ("polar_f64_2^24", nb.nrng_polar, 7, 1 << 24, nb.NRNG_F64, 8),
+                                     ("polar_f32_2^24", nb.nrng_polar, 7, 1 << 24, nb.NRNG_F32, 4)):
+        out = torch.empty(n * el // 4, dtype=torch.float32, device=dev)
+        if fn is nb.nrng_polar:
+            ms = timed(lambda: fn(seed, 0, n, 0.0, 1.0, out, dt, stream, None), 10)
+        else:
+            ms = timed(lambda: fn(seed, 0, n, 0.0, 1.0, out, dt, stream), 10)
+        small[key + "_normals_per_s"] = n / (ms * 1e-3)
+        del out
+    ex["small_configs"] = small
+
     # repeated fill: 64 graph replays of a 2^28 FP32 Polar fill
     nf = 1 << 28
     out = torch.empty(nf, dtype=torch.float32, device=dev)
@@ -588,6 +603,23 @@ def cpu_baseline(cfg, methods):
         t1 = time.perf_counter()
         fn(seed, 0, n)
         single[key + "_normals_per_s"] = n / (time.perf_counter() - t1)
+    # and on every host core: B1 split into chunks of whole pairs, Polar by a
+    # count pass, a prefix of the counts and a generate pass (the same oracle
+    # routines as above on disjoint chunks), for the small configurations and
+    # the 2^30 single streams
+    multi = {}
+    for key, fn, seed, n in (("b1_2^20", O.b1_parallel, 1, 1 << 20), ("polar_2^24", O.polar_parallel, 7, 1 << 24),
+                             ("b1_2^30", O.b1_parallel, 1, 1 << 30), ("polar_2^30", O.polar_parallel, 7, 1 << 30)):
+        piece = max(4096, n // 2 // (4 * cores))   # about four chunks per thread
+        kw = {"chunk_pairs": piece} if fn is O.b1_parallel else {"chunk": piece}
+        best = None
+        for _ in range(2 if n <= 1 << 24 else 1):   # the small ones: best of two
+            t1 = time.perf_counter()
+            r = fn(seed, 0, n, threads=cores, **kw)
+            t2 = time.perf_counter() - t1
+            best = t2 if best is None else min(best, t2)
+            del r
+        multi[key + "_normals_per_s"] = n / best
     try:
         affinity = len(os.sched_getaffinity(0))
     except (AttributeError, OSError):
@@ -595,7 +627,7 @@ def cpu_baseline(cfg, methods):
     return {"value": done / dt, "unit": "normals/s", "cores": cores, "nproc_affinity": affinity, "kind": "oracle",
             "sample": "the whole batched workload: %d streams x %s, %d normals, one FP64 oracle call per "
                       "stream on a %d-thread pool (%.1f s wall)" % (ns, "+".join(methods), done, cores, dt),
-            "single_thread": single}
+            "single_thread": single, "host_cores": multi}
 
 
 if __name__ == "__main__":

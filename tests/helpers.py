@@ -66,7 +66,14 @@ def fp32_tol(z_ref: np.ndarray, mu, sigma) -> np.ndarray:
 
 
 def fp64_scaled_tol(z_ref: np.ndarray, mu, sigma) -> np.ndarray:
-    """FP64 bar for z = sigma n + mu: 4 ulp of max(|z|, |mu|, sigma |n|)."""
+    """FP64 bar for z = sigma n + mu: 4 ulp of max(|z|, |mu|, sigma |n|).
+
+    With mu = 0 this is the plain 4-ulp bar on z.  With mu != 0 the sum can
+    cancel (|z| much smaller than sigma |n|): the kernel's and the oracle's
+    n agree to a few ulp of n, which after the cancellation is many ulp of
+    z (9 seen), so 4 ulp of |z| alone cannot be met by any correct FP64
+    evaluation.  Scaling by the larger of |mu| and sigma |n| bounds the
+    error that the final multiply-add itself can leave."""
     z = np.abs(z_ref)
     mu = np.asarray(mu, dtype=np.float64)
     sigma = np.asarray(sigma, dtype=np.float64)
@@ -78,7 +85,8 @@ def fp64_scaled_tol(z_ref: np.ndarray, mu, sigma) -> np.ndarray:
 
 def fp64_poly_tol(z_ref: np.ndarray, mu, sigma) -> np.ndarray:
     """FP64 bar for the methods that evaluate the Section 3 polynomial (P2
-    and B3): the 4-ulp bar of fp64_scaled_tol plus 4e-15 sigma |n|.  The two sides evaluate the same degree-15 polynomial
+    and B3): the 4-ulp bar of fp64_scaled_tol plus 4e-15 sigma |n|.  The
+    two sides evaluate the same degree-15 polynomial
     h(v) differently: the oracle sums the Chebyshev series by the three-term
     recurrence (measured error up to 6.7e-16 against 40-digit evaluation),
     the kernel uses Horner's rule on the monomial coefficients (2.2e-16);
