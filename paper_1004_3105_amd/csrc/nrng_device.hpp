@@ -134,6 +134,11 @@ __device__ __forceinline__ uint16_t f32_to_bf16_bits(float f)
 // halves are kept).
 __device__ __forceinline__ uint16_t f32_to_f16_bits(float f)
 {
+    // FP16 output is the FP32 value rounded to nearest even: two roundings.
+    // The empty asm keeps the compiler from fusing the FMA that produced f
+    // with this conversion into one mixed-precision FMA (v_fma_mixlo_f16),
+    // which rounds once and differs in rare near-tie cases.
+    asm("" : "+v"(f));
     _Float16 h = (_Float16)f;
     return __builtin_bit_cast(uint16_t, h);
 }
@@ -790,36 +795,6 @@ __device__ __forceinline__ uint64_t uniform_u64(uint64_t v)
     uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
     uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
     return ((uint64_t)hi << 32) | lo;
-}
-
-// Cross-lane moves by DPP over the whole wave64 (GFX9 wave shift / rotate).
-// wave_shr1_keep: lane l > 0 receives src of lane l - 1, lane 0 keeps old.
-// wave_ror1: lane l receives src of lane (l - 1) mod 64 (lane 0 gets lane 63).
-__device__ __forceinline__ uint32_t dpp_shr1_keep_u32(uint32_t old, uint32_t src)
-{
-    return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)src, 0x138, 0xF, 0xF, false);
-}
-__device__ __forceinline__ uint32_t dpp_ror1_u32(uint32_t src)
-{
-    return (uint32_t)__builtin_amdgcn_mov_dpp((int)src, 0x13C, 0xF, 0xF, false);   // no lane lacks a source
-}
-__device__ __forceinline__ float wave_shr1_keep(float old, float src)
-{
-    return __uint_as_float(dpp_shr1_keep_u32(__float_as_uint(old), __float_as_uint(src)));
-}
-__device__ __forceinline__ float wave_ror1(float src) { return __uint_as_float(dpp_ror1_u32(__float_as_uint(src))); }
-__device__ __forceinline__ double wave_shr1_keep(double old, double src)
-{
-    const uint64_t o = __builtin_bit_cast(uint64_t, old), v = __builtin_bit_cast(uint64_t, src);
-    const uint64_t r = (uint64_t)dpp_shr1_keep_u32((uint32_t)o, (uint32_t)v) |
-                       ((uint64_t)dpp_shr1_keep_u32((uint32_t)(o >> 32), (uint32_t)(v >> 32)) << 32);
-    return __builtin_bit_cast(double, r);
-}
-__device__ __forceinline__ double wave_ror1(double src)
-{
-    const uint64_t v = __builtin_bit_cast(uint64_t, src);
-    const uint64_t r = (uint64_t)dpp_ror1_u32((uint32_t)v) | ((uint64_t)dpp_ror1_u32((uint32_t)(v >> 32)) << 32);
-    return __builtin_bit_cast(double, r);
 }
 
 // Orders one wave's LDS accesses before and after this point for all of its

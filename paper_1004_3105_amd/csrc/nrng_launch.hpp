@@ -19,7 +19,7 @@ enum Mode { MODE_SINGLE = 0, MODE_BATCHED = 1, MODE_TRACE = 2, MODE_XY = 3 };
 //   generate  per tile, the accepted candidates are listed from the masks and
 //             the lanes of a wave each take consecutive accepted pairs, so
 //             that only accepted candidates are re-hashed and transformed and
-//             the output is written with aligned 16-byte stores.
+//             the output is written with one 16-byte store per lane and pass.
 // No kernel waits on another workgroup, and consecutive launches and graph
 // replays need no clearing of the workspace.
 constexpr uint32_t kChunkTiles = 16;

@@ -12,7 +12,8 @@ the oracle computes independently:
   consumed count, and of B2 and B3 (seed 1) at sampled output indices;
 * the batched workload of 4096 streams (about 4.4e8 normals per method, B1,
   Polar, P2, B3, Algorithm R and B2) in full: every value and every
-  consumed count of every stream;
+  consumed count of every stream; and its BF16 and FP16 outputs equal to the
+  FP32 output rounded to nearest even, bit for bit;
 * 64 graph-replayed fills of 2^28 FP32 Polar normals from one device cursor
   (2^34 normals of one stream): the final cursor against the oracle's count,
   and sampled slices of sampled fills, placed by the oracle's prefix, with
@@ -291,6 +292,40 @@ def test_batched_full_workload(method, capsys):
     with capsys.disabled():
         print("\n[batched method %d, all %d streams, %d values] worst error / bar %.3f" % (method, ns, total, worst),
               flush=True)
+
+
+@pytest.mark.parametrize("method", [nb.NRNG_METHOD_B1, nb.NRNG_METHOD_POLAR, nb.NRNG_METHOD_P2, nb.NRNG_METHOD_B3,
+                                    nb.NRNG_METHOD_R, nb.NRNG_METHOD_B2])
+def test_batched_full_workload_half_is_rounded_f32(method):
+    """BF16 and FP16 output of the whole batched workload equals the FP32
+    output of the same call rounded to nearest even, bit for bit (C15: the
+    value is computed in FP32 and rounded once more).  A conversion fused
+    with the final FMA into one mixed-precision instruction would round once
+    and differ in rare near-tie cases; about 4.4e8 values per method reach
+    such cases.  The consumed counts do not depend on the output type."""
+    d = dev()
+    cfg = synth.batched_streams()
+    ns, total = len(cfg["n"]), cfg["total"]
+    D = {k: torch.from_numpy(cfg[k].view(np.int64) if cfg[k].dtype == np.uint64 else cfg[k]).to(d)
+         for k in ("seed", "offset", "n", "mu", "sigma")}
+    nb.nrng_reserve(total, ns)
+    out32 = torch.empty(total, dtype=torch.float32, device=d)
+    c32 = torch.zeros(ns, dtype=torch.int64, device=d)
+    case("batched full workload f32", method, ns, total)
+    nb.nrng_batched(method, ns, D["seed"], D["offset"], D["n"], None, D["mu"], D["sigma"], out32, total,
+                    nb.NRNG_F32, None, c32)
+    for dtype in (nb.NRNG_BF16, nb.NRNG_F16):
+        out = torch.empty(total, dtype=TDT[dtype], device=d)
+        cons = torch.zeros(ns, dtype=torch.int64, device=d)
+        case("batched full workload", method, dtype, ns, total)
+        nb.nrng_batched(method, ns, D["seed"], D["offset"], D["n"], None, D["mu"], D["sigma"], out, total,
+                        dtype, None, cons)
+        torch.cuda.synchronize()
+        want = out32.to(TDT[dtype])
+        bad = int((out.view(torch.int16) != want.view(torch.int16)).sum().item())
+        assert bad == 0, (NAME[dtype], bad)
+        assert torch.equal(cons, c32)
+        del out, want
 
 
 def test_graph_fill_64_x_2e28_sampled():
