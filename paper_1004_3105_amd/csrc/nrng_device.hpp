@@ -86,27 +86,52 @@ __device__ __forceinline__ uint64_t sm_round1(const SmRun &r, uint32_t zl)
     return ((uint64_t)ph << 32) | (uint32_t)m;
 }
 
-// Top 32 bits of the hash, as splitmix64_mix_hi.
-__device__ __forceinline__ uint32_t sm_hi(const SmRun &r, uint32_t zl)
+// The rest of the hash from the first product p = (z ^ (z >> 30)) * C1:
+// its top 32 bits (as splitmix64_mix_hi) or all of it (as splitmix64_mix).
+__device__ __forceinline__ uint32_t sm_hi_of(uint64_t p)
 {
-    uint64_t z = sm_round1(r, zl);
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    const uint32_t h = (uint32_t)(z >> 32);
+    p = (p ^ (p >> 27)) * 0x94D049BB133111EBull;
+    const uint32_t h = (uint32_t)(p >> 32);
     return h ^ (h >> 31);
 }
+__device__ __forceinline__ uint64_t sm_full_of(uint64_t p)
+{
+    p = (p ^ (p >> 27)) * 0x94D049BB133111EBull;
+    return p ^ (p >> 31);
+}
+
+// Top 32 bits of the hash, as splitmix64_mix_hi.
+__device__ __forceinline__ uint32_t sm_hi(const SmRun &r, uint32_t zl) { return sm_hi_of(sm_round1(r, zl)); }
 
 // The full hash, as splitmix64_mix.
-__device__ __forceinline__ uint64_t sm_full(const SmRun &r, uint32_t zl)
-{
-    uint64_t z = sm_round1(r, zl);
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    return z ^ (z >> 31);
-}
+__device__ __forceinline__ uint64_t sm_full(const SmRun &r, uint32_t zl) { return sm_full_of(sm_round1(r, zl)); }
 
 // True when every z in [zb, zb + span) has the high word of zb (span >= 1).
 __device__ __forceinline__ bool sm_run_fits(uint64_t zb, uint64_t span)
 {
     return (uint64_t)(uint32_t)zb + (span - 1) <= 0xFFFFFFFFull;
+}
+
+// Even-odd pairs of counters.  An even z_e and z_o = z_e + 1 differ in bit 0
+// only, so z >> 30 is the same for both and the first round's xor-shift
+// gives results that differ in bit 0 only: z_o ^ (z_o >> 30) is one more
+// than z_e ^ (z_e >> 30) when bit 0 of the latter (bit 30 of z_e) is clear,
+// one less when it is set.  The first product is linear in its operand mod
+// 2^64, so its value for z_o is the one for z_e plus or minus C1: one 64-bit
+// add in place of the first round.  sm_pair_step gives that C1 or -C1 for
+// z_e; it is the same for every even z of a range in which bit 30 does not
+// change (sm_pair_fits), which also keeps the range's high word (sm_run).
+// The results are SplitMix64's, bit for bit.
+__device__ __forceinline__ uint64_t sm_pair_step(uint64_t z_e)
+{
+    return ((z_e >> 30) & 1) ? 0ull - 0xBF58476D1CE4E5B9ull : 0xBF58476D1CE4E5B9ull;
+}
+
+// True when every z in [zb, zb + span) has the bit 30 and the high word of
+// zb (no multiple of 2^30 inside; span >= 1).
+__device__ __forceinline__ bool sm_pair_fits(uint64_t zb, uint64_t span)
+{
+    return (uint64_t)((uint32_t)zb & 0x3FFFFFFFu) + (span - 1) <= 0x3FFFFFFFull;
 }
 
 // ---------------------------------------------------------------------------
