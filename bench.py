@@ -45,16 +45,22 @@ VALU_PEAK_TOPS = 39.32
 # word: counter add 1, first round on the low word 2, first product 3,
 # second round's 64-bit shift and two xors 3, top word of the second product
 # 4, final shift and xor 2) or 17 (full hash: the whole second product 4 and
-# the final 64-bit xor-shift 4).  A kernel's re-computation of work another
-# kernel already did (the generate kernels' second hash of each accepted
-# candidate) is not the method's work: it is listed in IMPL_OVERHEAD.
-#   polar_count:    per candidate: 2 top-word hashes 30 + S - 1 = X^2 + (Y^2 - 1)
-#                   by two multiply-adds 2 + the unsigned test 1
+# the final 64-bit xor-shift 4).  Of two consecutive counters whose z are
+# even and odd, the odd one's first product is the even one's plus or minus
+# the multiplier, one 64-bit add in place of its counter add, first round
+# and first product (6): it costs 10 (top word) or 12 (full).  A stream's
+# counters go in such pairs, so a candidate or pair of two counters takes one
+# of each, and B3's three counters per pair take 1.5 of the cheaper kind.  A
+# kernel's re-computation of work another kernel already did (the generate
+# kernels' second hash of each accepted candidate) is not the method's work:
+# it is listed in IMPL_OVERHEAD_PAIRED and IMPL_OVERHEAD_UNPAIRED.
+#   polar_count:    per candidate: top-word hashes of X 15 and Y 10 + S - 1 =
+#                   X^2 + (Y^2 - 1) by two multiply-adds 2 + the unsigned test 1
 #   polar_generate: per pair: the FP32 radius with the exact complement near
 #                   s = 1 (complement and select 5, conversion 4, remainder
 #                   and selects 7, log and reciprocal square root 2,
 #                   scalings 4) 22 + 2 conversions and 2 FMAs 4
-#   b1_batched:     per pair: full hash of u 17 + top-word hash of v 15 +
+#   b1_batched:     per pair: full hash of u 17 + top-word hash of v 10 +
 #                   ln(1 - u) with the exact complement 21 + angle reduction,
 #                   conversion, sin, cos 9 + 2 FMAs
 #   p2_count:       per candidate: as polar_count, the one-sided test S < 2^62
@@ -62,12 +68,13 @@ VALU_PEAK_TOPS = 39.32
 #                   degree-9 Horner 9 + split test and select 2 + the library
 #                   branch for s > 8/9 (10 operations, taken by 1/9 of the
 #                   pairs) 1 + scaling 1 + 2 conversions and 2 FMAs 4
-#   b3_batched:     per pair: full hashes of u1 and u2 (17 each) and the top
-#                   word of u3 (15) + m = max 3 + conversion 3 + u = m^2 1 + v 4 +
+#   b3_batched:     per pair: full hashes of u1 and u2 and the top word of u3
+#                   (17 + 17 + 15, less 5 for each of the 1.5 odd counters of
+#                   a pair) 41.5 + m = max 3 + conversion 3 + u = m^2 1 + v 4 +
 #                   degree-9 Horner 9 + scaling 2 + the library branch's 9
 #                   operations for the 1/9 of pairs above 8/9 1 + split test and
 #                   select 2 + angle reduction, conversion, sin, cos 8 + 2 FMAs
-#   ratio_count:    per candidate: 2 full hashes 34 + v - 1/2 and 1 - u as
+#   ratio_count:    per candidate: 2 full hashes 17 + 12 + v - 1/2 and 1 - u as
 #                   integers 4 + their conversions (signed split 5, unsigned
 #                   3) 8 + x = c dv / du 3 + x^2 1 + -4 ln(1 - u) (scale, log,
 #                   scale) 3 + the comparison 1 + the FP32 screening band
@@ -75,32 +82,38 @@ VALU_PEAK_TOPS = 39.32
 #                   the band (under 1e-4 of candidates) 0
 #   ratio_generate: per output: the integer differences 4 + conversions 8 +
 #                   x 3 + 1 FMA
-#   b2_batched:     per pair: full hash of u 17 + top-word hash of v 15 +
+#   b2_batched:     per pair: full hash of u 17 + top-word hash of v 10 +
 #                   ln(1 - u) with the exact complement 21 + quarter-turn
 #                   reduction, conversion and scaling of y 6 + t = y^2 and
 #                   the two polynomials (6 FMAs, 1 product) 8 + four
 #                   doublings (d = 2s, s' = d c, c' = 1 - d s) 12 + 2 FMAs
-ALU_OPS = {"polar_count": 33, "polar_generate": 26, "b1_batched": 64, "p2_count": 33, "p2_generate": 22,
-           "b3_batched": 84, "ratio_count": 58, "ratio_generate": 16, "b2_batched": 81}
+ALU_OPS = {"polar_count": 28, "polar_generate": 26, "b1_batched": 59, "p2_count": 28, "p2_generate": 22,
+           "b3_batched": 76.5, "ratio_count": 53, "ratio_generate": 16, "b2_batched": 76}
 # What the generate kernels compute again per unit, beyond the method's own
-# work: the two hashes of the accepted candidate and S (P, P2: 2 x 15 + 2),
-# the two full hashes (R: 2 x 17).
-IMPL_OVERHEAD = {"polar_generate": 32, "p2_generate": 32, "ratio_generate": 34}
+# work: the two hashes of the accepted candidate and S (P, P2), or the two
+# full hashes (R).  The kernel forms the second hash from the first's
+# product when the candidate's counters are an even-odd pair (a stream whose
+# z = c + gamma starts even: 15 + 10 + 2 for P and P2, 17 + 12 for R) and in
+# full otherwise (15 + 15 + 2, 17 + 17); recomputed_ops() weighs the two by
+# the workload's share of pairs in each kind of stream.
+IMPL_OVERHEAD_PAIRED = {"polar_generate": 27, "p2_generate": 27, "ratio_generate": 29}
+IMPL_OVERHEAD_UNPAIRED = {"polar_generate": 32, "p2_generate": 32, "ratio_generate": 34}
 # The same counts by instruction class, for weighting by the measured issue
 # cost of each class (extras "valu_issue_cost"): 32-bit multiplies and
-# 32 x 32 -> 64-bit multiply-adds (5 in a hash), 64-bit shifts (1 in a
-# hash), 64-bit adds, transcendentals (log, sqrt, rcp, rsq, sin, cos), and
-# the rest (FMA-like, cost 1).
+# 32 x 32 -> 64-bit multiply-adds (5 in a hash, 3 in the odd counter's),
+# 64-bit shifts (1 in a hash), 64-bit adds (the odd counter's product, the
+# counter conversion of B1's radius), transcendentals (log, sqrt, rcp, rsq,
+# sin, cos), and the rest (FMA-like, cost 1).
 ALU_MIX = {
-    "polar_count": {"mul": 12, "shr64": 2, "add64": 0, "trans": 0, "other": 19},
+    "polar_count": {"mul": 10, "shr64": 2, "add64": 1, "trans": 0, "other": 15},
     "polar_generate": {"mul": 0, "shr64": 0, "add64": 1, "trans": 2, "other": 23},
-    "b1_batched": {"mul": 10, "shr64": 2, "add64": 1, "trans": 4, "other": 47},
-    "p2_count": {"mul": 12, "shr64": 2, "add64": 0, "trans": 0, "other": 19},
+    "b1_batched": {"mul": 8, "shr64": 2, "add64": 2, "trans": 4, "other": 43},
+    "p2_count": {"mul": 10, "shr64": 2, "add64": 1, "trans": 0, "other": 15},
     "p2_generate": {"mul": 0, "shr64": 0, "add64": 0, "trans": 1, "other": 21},
-    "b3_batched": {"mul": 15, "shr64": 3, "add64": 0, "trans": 3, "other": 63},
-    "ratio_count": {"mul": 10, "shr64": 2, "add64": 0, "trans": 2, "other": 44},
+    "b3_batched": {"mul": 12, "shr64": 3, "add64": 1.5, "trans": 3, "other": 57},
+    "ratio_count": {"mul": 8, "shr64": 2, "add64": 1, "trans": 2, "other": 40},
     "ratio_generate": {"mul": 0, "shr64": 0, "add64": 0, "trans": 1, "other": 15},
-    "b2_batched": {"mul": 10, "shr64": 2, "add64": 1, "trans": 2, "other": 66},
+    "b2_batched": {"mul": 8, "shr64": 2, "add64": 2, "trans": 2, "other": 62},
 }
 ALU_UNIT = {"polar_count": "candidate", "polar_generate": "output pair", "b1_batched": "output pair",
             "p2_count": "candidate", "p2_generate": "output pair", "b3_batched": "output pair",
@@ -169,6 +182,23 @@ def read_profile_avg(kernel_tag: str):
         return float(kv["avg_ms"])
     except (KeyError, ValueError):
         return None
+
+
+def paired_share(cfg) -> float:
+    """Share of the workload's outputs in streams whose first z = seed +
+    offset + gamma is even (their candidates' two counters are an even-odd
+    pair)."""
+    import numpy as np
+    n = cfg["n"].astype(np.float64)
+    z0 = cfg["seed"].astype(np.uint64) + cfg["offset"].astype(np.uint64) + np.uint64(0x9E3779B97F4A7C15)
+    even = (z0 & np.uint64(1)) == 0
+    return float(n[even].sum() / max(n.sum(), 1.0))
+
+
+def recomputed_ops(kernel: str, share: float) -> float:
+    """Operations per unit the generate kernel computes again (IMPL_OVERHEAD_*),
+    weighed by the share of the workload in paired streams."""
+    return round(share * IMPL_OVERHEAD_PAIRED[kernel] + (1 - share) * IMPL_OVERHEAD_UNPAIRED[kernel], 2)
 
 
 def median(xs):
@@ -312,7 +342,7 @@ def main() -> int:
             per_kernel[name]["alu_method"] = {
                 "ms": round(exec_ms, 5), "ops": ops,
                 "frac_valu_peak": round(ops / (exec_ms * 1e-3) / 1e12 / VALU_PEAK_TOPS, 4),
-                "generate_recomputed_ops_per_unit": IMPL_OVERHEAD[name + "_generate"]}
+                "generate_recomputed_ops_per_unit": recomputed_ops(name + "_generate", paired_share(cfg))}
 
     # dominant kernel -> roofline (ALU-bound: VALU lane operations on the
     # method's own work), with its HBM write rate beside (bytes: the output
@@ -330,8 +360,8 @@ def main() -> int:
                 "algorithmic_write_bytes_per_launch": wbytes,
                 "hbm": {"achieved_GBps": round(wbytes / (kern[dom]["ms"] * 1e-3) / 1e9, 1), "peak_GBps": HBM_PEAK_GBS,
                         "frac": round(wbytes / (kern[dom]["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}}
-    if dom in IMPL_OVERHEAD:
-        roofline["recomputed_ops_per_unit"] = IMPL_OVERHEAD[dom]
+    if dom in IMPL_OVERHEAD_PAIRED:
+        roofline["recomputed_ops_per_unit"] = recomputed_ops(dom, paired_share(cfg))
     prof = read_profile_avg("batched_%s_f32" % dom)
     if prof is not None:
         roofline["rocprof_avg_ms"] = prof
