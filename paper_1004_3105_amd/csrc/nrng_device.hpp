@@ -100,6 +100,14 @@ __device__ __forceinline__ uint64_t sm_full_of(uint64_t p)
     return p ^ (p >> 31);
 }
 
+// The top word of the second product, before the final xor-shift: the top
+// word of the hash is h ^ (h >> 31) (sm_hi_of).
+__device__ __forceinline__ uint32_t sm_top_raw_of(uint64_t p)
+{
+    p = (p ^ (p >> 27)) * 0x94D049BB133111EBull;
+    return (uint32_t)(p >> 32);
+}
+
 // Top 32 bits of the hash, as splitmix64_mix_hi.
 __device__ __forceinline__ uint32_t sm_hi(const SmRun &r, uint32_t zl) { return sm_hi_of(sm_round1(r, zl)); }
 
@@ -419,6 +427,25 @@ __device__ __forceinline__ bool polar_accept_xy(int32_t X, int32_t Y)
 {
     const uint64_t sm1 = (uint64_t)((int64_t)X * (int64_t)X + sq_minus_one(Y));
     return sm1 < (1ull << 62) - 1;
+}
+
+// Algorithm P's test (P2's with p2 set) decided from the raw top words hx,
+// hy of the candidate's two hashes (sm_top_raw_of), without their final
+// xor-shift: X = hx ^ (hx >> 31) differs from X' = (int32) hx by at most 1
+// (only bit 0 can change), so S' = X'^2 + Y'^2 is within 2^33 of S, and
+// S' = 0 exactly when S = 0.  The test on S' therefore equals the test on S
+// unless |S' - 2^62| <= 2^34; `band` flags those candidates (about one in
+// 10^8), for which the caller decides on X and Y themselves.
+template <bool P2>
+__device__ __forceinline__ bool polar_screen_raw(uint32_t hx, uint32_t hy, bool &band)
+{
+    const int32_t x = (int32_t)hx, y = (int32_t)hy;
+    const uint64_t sm1 = (uint64_t)((int64_t)x * (int64_t)x + sq_minus_one(y));   // S' - 1
+    band = sm1 - ((1ull << 62) - 1 - (1ull << 34)) < (1ull << 35);
+    if constexpr (P2)
+        return sm1 + 1 < (1ull << 62);      // S' < 2^62 (S' = 0 included)
+    else
+        return sm1 < (1ull << 62) - 1;      // 0 < S' < 2^62
 }
 
 // 2 piece + (bit `lane` of m): one v_addc with the lane mask m as its carry

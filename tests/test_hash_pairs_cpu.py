@@ -1,4 +1,5 @@
-"""The identity behind the kernels' even-odd counter pairs (CPU, no GPU).
+"""Integer identities the kernels rely on (CPU, no GPU): even-odd counter
+pairs, and the accept test screened on raw hash words.
 
 SplitMix64's first round maps z to (z ^ (z >> 30)) * C1 mod 2^64.  For an
 even z and z + 1 the xor-shift results differ in bit 0 only, so the odd
@@ -43,3 +44,37 @@ def test_identity_needs_the_even_counter_first():
     # in general (the kernels never pair an odd counter with the next one)
     for z in ((1 << 30) - 1, (1 << 32) - 1, 0x123456789ABCDEF1, (3 << 40) - 1):
         assert round1(z + 1) != (round1(z) + step(z)) & M64, hex(z)
+
+
+def _s32(h: int) -> int:
+    return h - (1 << 32) if h >= 1 << 31 else h
+
+
+def test_accept_screen_on_raw_top_words():
+    """The mask kernels decide Algorithm P's (and P2's) test on the top words
+    h of the two hashes before their final xor-shift (X = h ^ (h >> 31) moves
+    only bit 0), and decide exactly only when S' lies within 2^34 of 2^62.
+    Outside that band the screened decision equals the exact one, checked on
+    random words and on candidates next to the circle s = 1."""
+    rng = synth.rng(0x5C2)
+    cases = [tuple(int(v) for v in rng.integers(0, 1 << 32, 2, dtype=np.uint64)) for _ in range(100000)]
+    t = rng.uniform(0, 2 * np.pi, 100000)
+    r = 2.0**31 * (1 + rng.uniform(-2.0**-26, 2.0**-26, t.size))
+    for X, Y in zip(np.clip(np.rint(r * np.cos(t)), -2**31, 2**31 - 1), np.clip(np.rint(r * np.sin(t)), -2**31, 2**31 - 1)):
+        hx, hy = int(X) & 0xFFFFFFFF, int(Y) & 0xFFFFFFFF
+        cases.append((hx ^ 1 if hx >> 31 else hx, hy ^ 1 if hy >> 31 else hy))
+    cases += [(0, 0), (1, 0), (0, 1), (0xFFFFFFFF, 0), (0x80000000, 0), (0x80000001, 0x80000000)]
+    banded = 0
+    for hx, hy in cases:
+        X, Y = _s32(hx ^ (hx >> 31)), _s32(hy ^ (hy >> 31))
+        S = X * X + Y * Y
+        x, y = _s32(hx), _s32(hy)
+        sm1 = (x * x + y * y - 1) & M64
+        band = ((sm1 - ((1 << 62) - 1 - (1 << 34))) & M64) < (1 << 35)
+        banded += band
+        if band:
+            assert abs(S - (1 << 62)) <= (1 << 35)
+            continue
+        assert (sm1 < (1 << 62) - 1) == (0 < S < (1 << 62)), (hx, hy)            # P
+        assert (((sm1 + 1) & M64) < (1 << 62)) == (S < (1 << 62)), (hx, hy)      # P2
+    assert banded > 1000   # the near-circle cases reach the exact path
