@@ -54,8 +54,13 @@ VALU_PEAK_TOPS = 39.32
 # kernel's re-computation of work another kernel already did (the generate
 # kernels' second hash of each accepted candidate) is not the method's work:
 # it is listed in IMPL_OVERHEAD_PAIRED and IMPL_OVERHEAD_UNPAIRED.
-#   polar_count:    per candidate: top-word hashes of X 15 and Y 10 + S - 1 =
-#                   X^2 + (Y^2 - 1) by two multiply-adds 2 + the unsigned test 1
+#   polar_count:    per candidate: top words of the hashes of X 13 and Y 8,
+#                   each without the final xor-shift (2; it moves only bit 0,
+#                   so S' from these words is within 2^33 of S) + S' - 1 =
+#                   X'^2 + (Y'^2 - 1) by two multiply-adds 2 + the unsigned test
+#                   1 + the test for S' within 2^34 of 2^62 (64-bit add and
+#                   compare) 2; the exact test for such a wave (about one in
+#                   10^6 waves) 0
 #   polar_generate: per pair: the FP32 radius with the exact complement near
 #                   s = 1 (complement and select 5, conversion 4, remainder
 #                   and selects 7, log and reciprocal square root 2,
@@ -63,7 +68,7 @@ VALU_PEAK_TOPS = 39.32
 #   b1_batched:     per pair: full hash of u 17 + top-word hash of v 10 +
 #                   ln(1 - u) with the exact complement 21 + angle reduction,
 #                   conversion, sin, cos 9 + 2 FMAs
-#   p2_count:       per candidate: as polar_count, the one-sided test S < 2^62
+#   p2_count:       per candidate: as polar_count, the one-sided test S' < 2^62
 #   p2_generate:    per pair: s from the top word 1 + v = (6s - 4)/(4 - 3s) 4 +
 #                   degree-9 Horner 9 + split test and select 2 + the library
 #                   branch for s > 8/9 (10 operations, taken by 1/9 of the
@@ -87,7 +92,7 @@ VALU_PEAK_TOPS = 39.32
 #                   reduction, conversion and scaling of y 6 + t = y^2 and
 #                   the two polynomials (6 FMAs, 1 product) 8 + four
 #                   doublings (d = 2s, s' = d c, c' = 1 - d s) 12 + 2 FMAs
-ALU_OPS = {"polar_count": 28, "polar_generate": 26, "b1_batched": 59, "p2_count": 28, "p2_generate": 22,
+ALU_OPS = {"polar_count": 26, "polar_generate": 26, "b1_batched": 59, "p2_count": 26, "p2_generate": 22,
            "b3_batched": 76.5, "ratio_count": 53, "ratio_generate": 16, "b2_batched": 76}
 # What the generate kernels compute again per unit, beyond the method's own
 # work: the two hashes of the accepted candidate and S (P, P2), or the two
@@ -105,10 +110,10 @@ IMPL_OVERHEAD_UNPAIRED = {"polar_generate": 32, "p2_generate": 32, "ratio_genera
 # counter conversion of B1's radius), transcendentals (log, sqrt, rcp, rsq,
 # sin, cos), and the rest (FMA-like, cost 1).
 ALU_MIX = {
-    "polar_count": {"mul": 10, "shr64": 2, "add64": 1, "trans": 0, "other": 15},
+    "polar_count": {"mul": 10, "shr64": 2, "add64": 2, "trans": 0, "other": 12},
     "polar_generate": {"mul": 0, "shr64": 0, "add64": 1, "trans": 2, "other": 23},
     "b1_batched": {"mul": 8, "shr64": 2, "add64": 2, "trans": 4, "other": 43},
-    "p2_count": {"mul": 10, "shr64": 2, "add64": 1, "trans": 0, "other": 15},
+    "p2_count": {"mul": 10, "shr64": 2, "add64": 2, "trans": 0, "other": 12},
     "p2_generate": {"mul": 0, "shr64": 0, "add64": 0, "trans": 1, "other": 21},
     "b3_batched": {"mul": 12, "shr64": 3, "add64": 1.5, "trans": 3, "other": 57},
     "ratio_count": {"mul": 8, "shr64": 2, "add64": 1, "trans": 2, "other": 40},
