@@ -143,7 +143,8 @@ def kernel_source_hash() -> str:
     h = hashlib.sha256()
     for f in ("nrng_kernels.hpp", "nrng_kernels_p.hip", "nrng_kernels_p2.hip", "nrng_kernels_r.hip",
               "nrng_kernels_b1.hip", "nrng_kernels_b3.hip", "nrng_kernels_b2.hip", "nrng_kernels_misc.hip",
-              "nrng_device.hpp", "nrng_p2_poly.hpp", "nrng_b2_poly.hpp"):
+              "nrng_device.hpp", "nrng_p2_poly.hpp", "nrng_b2_poly.hpp",
+              "nrng_abi.cpp"):   # the compiled launch defaults pick the variant profiled
         with open(os.path.join(ROOT, "paper_1004_3105_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
