@@ -313,6 +313,22 @@ int nrng_batched_exec_part(int part, int method, uint32_t nstreams, const uint64
                            const double *d_mu, const double *d_sigma, void *out, int dtype, void *stream,
                            uint64_t *d_consumed);
 
+/* nrng_batched_exec with its main kernel timed: the same launches, results
+ * and errors, except that the main kernel (the Box-Muller family's batched
+ * kernel, or the Polar, P2 or R generate kernel) is dispatched with
+ * hipExtLaunchKernel so that ev_start and ev_stop record that dispatch's own
+ * start and end.  No marker is added to the stream, so timing a step this
+ * way does not lengthen it, and hipEventElapsedTime(ev_start, ev_stop) is
+ * the kernel's duration alone.
+ *   ev_start, ev_stop  hipEvent_t handles created by the caller (with
+ *                      timing enabled) on the stream's device; both are
+ *                      required (NRNG_EINVAL if either is NULL).
+ * The events are not recorded when nothing is launched (nstreams 0, or an
+ * error return). */
+int nrng_batched_exec_timed(int method, uint32_t nstreams, const uint64_t *d_seed, const uint64_t *d_offset,
+                            const uint64_t *d_n, const uint64_t *d_out_off, const double *d_mu, const double *d_sigma,
+                            void *out, int dtype, void *stream, uint64_t *d_consumed, void *ev_start, void *ev_stop);
+
 /* ------------------------------------------------------------------------
  * Repeated fills through a HIP graph: capture one nrng_polar_dev launch
  * (with the workspace reserved beforehand) and return an instantiated graph

@@ -43,6 +43,7 @@ _SIGS = {
     "nrng_batched_plan": (_i32, [_i32, _u32, _vp, _vp, _u64, _i32, _vp, _vp]),
     "nrng_batched_exec": (_i32, [_i32, _u32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp]),
     "nrng_batched_exec_part": (_i32, [_i32, _i32, _u32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp]),
+    "nrng_batched_exec_timed": (_i32, [_i32, _u32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp]),
     "nrng_fillgraph_create": (_i32, [_u64, _vp, _u64, _f64, _f64, _vp, _i32, _vp, ctypes.POINTER(_vp)]),
     "nrng_fillgraph_launch": (_i32, [_vp, _vp]),
     "nrng_fillgraph_destroy": (_i32, [_vp]),
@@ -245,6 +246,28 @@ def nrng_batched_exec_part(part, method, nstreams, d_seed, d_offset, d_n, d_out_
            lib().nrng_batched_exec_part(part, method, nstreams, _ptr(d_seed), _ptr(d_offset), _ptr(d_n),
                                         _ptr(d_out_off), _ptr(d_mu), _ptr(d_sigma), _ptr(out), dtype,
                                         _stream(stream), _ptr(d_consumed)))
+
+
+def _event(e):
+    """A hipEvent_t handle from a torch.cuda.Event (which must have been
+    recorded once, so that torch has created it) or an int handle."""
+    if isinstance(e, int):
+        return e
+    h = getattr(e, "cuda_event", 0)
+    if not h:
+        raise ValueError("event expected (a torch.cuda.Event recorded once, or a hipEvent_t handle)")
+    return h
+
+
+def nrng_batched_exec_timed(method, nstreams, d_seed, d_offset, d_n, d_out_off, d_mu, d_sigma, out, dtype,
+                            stream, d_consumed, ev_start, ev_stop) -> None:
+    for t, nm in ((d_seed, "d_seed"), (d_offset, "d_offset"), (d_n, "d_n"), (d_out_off, "d_out_off"),
+                  (d_mu, "d_mu"), (d_sigma, "d_sigma"), (d_consumed, "d_consumed")):
+        _need(t, 8 * nstreams, "nrng_batched_exec_timed " + nm)
+    _check("nrng_batched_exec_timed",
+           lib().nrng_batched_exec_timed(method, nstreams, _ptr(d_seed), _ptr(d_offset), _ptr(d_n), _ptr(d_out_off),
+                                         _ptr(d_mu), _ptr(d_sigma), _ptr(out), dtype, _stream(stream),
+                                         _ptr(d_consumed), _event(ev_start), _event(ev_stop)))
 
 
 def nrng_fillgraph_create(seed, d_cursor, n, mu, sigma, out, dtype, stream) -> int:

@@ -727,10 +727,12 @@ int nrng_batched_exec(int method, uint32_t nstreams, const uint64_t *d_seed, con
                                   stream, d_consumed);
 }
 
-int nrng_batched_exec_part(int part, int method, uint32_t nstreams, const uint64_t *d_seed,
-                           const uint64_t *d_offset, const uint64_t *d_n, const uint64_t *d_out_off,
-                           const double *d_mu, const double *d_sigma, void *out, int dtype, void *stream,
-                           uint64_t *d_consumed)
+// exec over the latest plan: part 0 = the whole launch sequence, 1 = the
+// count kernels, 2 = the main kernel; ev0 / ev1 (may be null) record the
+// main kernel's own start and end.
+static int batched_exec(int part, int method, uint32_t nstreams, const uint64_t *d_seed, const uint64_t *d_offset,
+                        const uint64_t *d_n, const uint64_t *d_out_off, const double *d_mu, const double *d_sigma,
+                        void *out, int dtype, void *stream, uint64_t *d_consumed, hipEvent_t ev0, hipEvent_t ev1)
 {
     if (part < 0 || part > 2)
         return NRNG_EINVAL;
@@ -774,7 +776,7 @@ int nrng_batched_exec_part(int part, int method, uint32_t nstreams, const uint64
             return NRNG_OK;   // the Box-Muller family has no count pass
         const int bm = bm_of_method(method);
         const uint32_t grid = persistent_grid(*d, b1_blocks_per_cu(*d, 1, bm, dtype, tu.vi), tu.grid_per_cu, 0);
-        return hip_status(launch_b1_batched(bm, dtype, tu.vi, a, grid, s));
+        return hip_status(launch_b1_batched(bm, dtype, tu.vi, a, grid, s, ev0, ev1));
     }
     PolarArgs a = polar_args(*d);
     a.mu = 0.0;
@@ -794,7 +796,26 @@ int nrng_batched_exec_part(int part, int method, uint32_t nstreams, const uint64
     const uint32_t gm = persistent_grid(*d, polar_mask_blocks_per_cu(*d, MODE_BATCHED, vm, tu.vi), 0, 0);
     const uint32_t gg =
         persistent_grid(*d, polar_blocks_per_cu(*d, MODE_BATCHED, vm, dtype, tu.vi), tu.grid_per_cu, 0);
-    return hip_status(launch_polar(MODE_BATCHED, vm, dtype, tu.vi, a, gm, gg, s, part));
+    return hip_status(launch_polar(MODE_BATCHED, vm, dtype, tu.vi, a, gm, gg, s, part, ev0, ev1));
+}
+
+int nrng_batched_exec_part(int part, int method, uint32_t nstreams, const uint64_t *d_seed,
+                           const uint64_t *d_offset, const uint64_t *d_n, const uint64_t *d_out_off,
+                           const double *d_mu, const double *d_sigma, void *out, int dtype, void *stream,
+                           uint64_t *d_consumed)
+{
+    return batched_exec(part, method, nstreams, d_seed, d_offset, d_n, d_out_off, d_mu, d_sigma, out, dtype, stream,
+                        d_consumed, nullptr, nullptr);
+}
+
+int nrng_batched_exec_timed(int method, uint32_t nstreams, const uint64_t *d_seed, const uint64_t *d_offset,
+                            const uint64_t *d_n, const uint64_t *d_out_off, const double *d_mu, const double *d_sigma,
+                            void *out, int dtype, void *stream, uint64_t *d_consumed, void *ev_start, void *ev_stop)
+{
+    if (!ev_start || !ev_stop)
+        return NRNG_EINVAL;
+    return batched_exec(0, method, nstreams, d_seed, d_offset, d_n, d_out_off, d_mu, d_sigma, out, dtype, stream,
+                        d_consumed, (hipEvent_t)ev_start, (hipEvent_t)ev_stop);
 }
 
 int nrng_batched(int method, uint32_t nstreams, const uint64_t *d_seed, const uint64_t *d_offset,

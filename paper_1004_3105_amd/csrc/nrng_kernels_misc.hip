@@ -2,6 +2,8 @@
 // fixed scratch of the allocation-free entry point, probes), the polar scan
 // kernel instances, and the launchers that dispatch to the family
 // translation units (nrng_kernels_*.hip).
+#include <hip/hip_ext.h>
+
 #include "nrng_kernels.hpp"
 
 namespace nrng {
@@ -36,11 +38,12 @@ __global__ __launch_bounds__(1024) void prep_kernel(PrepArgs a)
     // B1, B3 and B2 (methods 0, 3 and 5): tiles of `unit` pairs; Polar, P2
     // and R: the candidate budget in words, in tiles of `unit` words
     const bool bm_family = a.method == 0 || a.method == 3 || a.method == 5;
-    auto words_of = [&](uint64_t n) -> uint64_t { return method_budget_words(a.method, n); };
-    auto tiles_of = [&](uint64_t n) -> uint64_t {
-        if (bm_family)
-            return ((n + 1) / 2 + a.unit - 1) / a.unit;
-        return (words_of(n) + a.unit - 1) / a.unit;
+    // tiles of `unit` pairs or words: a shift when unit is a power of two
+    // (every launch variant's is), else a 64-bit division
+    const bool unit_pow2 = (a.unit & (a.unit - 1)) == 0;
+    const uint32_t unit_log2 = (uint32_t)__builtin_ctzll(a.unit);
+    auto tiles_in = [&](uint64_t x) -> uint64_t {
+        return unit_pow2 ? (x + a.unit - 1) >> unit_log2 : (x + a.unit - 1) / a.unit;
     };
 
     uint64_t ncarry = 0, tcarry = 0, vcarry = 0;   // saturating sums over earlier chunks
@@ -67,11 +70,13 @@ __global__ __launch_bounds__(1024) void prep_kernel(PrepArgs a)
             }
         }
         bool valid[P];
-        uint64_t tl[P], tsum = 0, vsum = 0;
+        uint64_t tl[P], wd[P], tsum = 0, vsum = 0;
 #pragma unroll
         for (uint32_t i = 0; i < P; ++i) {
             valid[i] = j0 + i < NS && n[i] <= a.out_len && off[i] <= a.out_len - n[i];
-            tl[i] = valid[i] ? tiles_of(n[i]) : 0;
+            // the candidate budget of a rejection stream, computed once
+            wd[i] = (!bm_family && valid[i]) ? method_budget_words(a.method, n[i]) : 0;
+            tl[i] = valid[i] ? tiles_in(bm_family ? (n[i] + 1) / 2 : wd[i]) : 0;
             tsum = sat_add(tsum, tl[i]);
             vsum = sat_add(vsum, valid[i] ? n[i] : 0);
         }
@@ -92,7 +97,7 @@ __global__ __launch_bounds__(1024) void prep_kernel(PrepArgs a)
             a.tile_start[j] = tr;
             tr += tl[i];
             if (a.stream_words)
-                a.stream_words[j] = valid[i] ? words_of(n[i]) : 0;
+                a.stream_words[j] = wd[i];
             if (!a.out_off)
                 a.packed_off[j] = valid[i] ? off[i] : 0;
             if (a.consumed) {
@@ -271,11 +276,14 @@ static const void *polar_scan_ptr(int mode)
     return nullptr;
 }
 
-static int launch_args(const void *fn, uint32_t grid, uint32_t block, void *argp, hipStream_t s)
+static int launch_args(const void *fn, uint32_t grid, uint32_t block, void *argp, hipStream_t s,
+                       hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr)
 {
     if (!fn)
         return (int)hipErrorInvalidValue;
     void *args[] = {argp};
+    if (ev0 || ev1)   // the events take the dispatch's own start and end times
+        return (int)hipExtLaunchKernel(fn, dim3(grid), dim3(block), args, 0, s, ev0, ev1, 0);
     return (int)hipLaunchKernel(fn, dim3(grid), dim3(block), args, 0, s);
 }
 
@@ -285,10 +293,11 @@ int launch_b1_single(int bm, int dtype, int vi, const B1Args &a, uint32_t grid, 
     return launch_args(b1_ptr(0, bm, dtype, vi), grid, kB1Variants[vi].wg, &c, s);
 }
 
-int launch_b1_batched(int bm, int dtype, int vi, const B1Args &a, uint32_t grid, hipStream_t s)
+int launch_b1_batched(int bm, int dtype, int vi, const B1Args &a, uint32_t grid, hipStream_t s, hipEvent_t ev0,
+                      hipEvent_t ev1)
 {
     B1Args c = a;
-    return launch_args(b1_ptr(1, bm, dtype, vi), grid, kB1Variants[vi].wg, &c, s);
+    return launch_args(b1_ptr(1, bm, dtype, vi), grid, kB1Variants[vi].wg, &c, s, ev0, ev1);
 }
 
 int launch_b1_words(int bm, int dtype, const B1Args &a, uint64_t npairs, hipStream_t s)
@@ -306,7 +315,7 @@ int launch_b1_words(int bm, int dtype, const B1Args &a, uint64_t npairs, hipStre
 }
 
 int launch_polar(int mode, int vm, int dtype, int vi, const PolarArgs &a, uint32_t grid_mask, uint32_t grid_gen,
-                 hipStream_t s, int part)
+                 hipStream_t s, int part, hipEvent_t ev0, hipEvent_t ev1)
 {
     PolarArgs c = a;
     const void *gen = polar_gen_ptr(mode, vm, dtype, vi);
@@ -319,7 +328,7 @@ int launch_polar(int mode, int vm, int dtype, int vi, const PolarArgs &a, uint32
             rc = launch_args(polar_scan_ptr(mode), 1, 1024, &c, s);
     }
     if (rc == (int)hipSuccess && part != 1)
-        rc = launch_args(gen, grid_gen, kPolarVariants[vi].wg, &c, s);
+        rc = launch_args(gen, grid_gen, kPolarVariants[vi].wg, &c, s, ev0, ev1);
     return rc;
 }
 

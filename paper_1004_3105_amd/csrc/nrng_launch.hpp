@@ -96,14 +96,18 @@ int polar_variants(const Variant **v);
 // B1 family: bm 0 = Algorithm B1, 1 = method B3.
 int launch_b1_single(int bm, int dtype, int vi, const B1Args &a, uint32_t grid, hipStream_t s);
 int launch_b1_words(int bm, int dtype, const B1Args &a, uint64_t npairs, hipStream_t s);
-int launch_b1_batched(int bm, int dtype, int vi, const B1Args &a, uint32_t grid, hipStream_t s);
+// ev0 / ev1 (either may be null): events that record the batched kernel's
+// own start and end (hipExtLaunchKernel), with no marker in the stream.
+int launch_b1_batched(int bm, int dtype, int vi, const B1Args &a, uint32_t grid, hipStream_t s,
+                      hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // Polar: the mask, scan and generate kernels, in that order on stream s.
 // vm selects the value method: 0 = Algorithm P, 1 = method P2 (no trace
-// mode), 2 = Algorithm R (one output element per accepted candidate).  grid_mask / grid_gen are the persistent grid sizes of the first and
-// last.  part 0 launches all three, 1 the mask and scan kernels, 2 the
-// generate kernel.
+// mode), 2 = Algorithm R (one output element per accepted candidate).
+// grid_mask / grid_gen are the persistent grid sizes of the first and last.
+// part 0 launches all three, 1 the mask and scan kernels, 2 the generate
+// kernel; ev0 / ev1 as for launch_b1_batched, on the generate kernel.
 int launch_polar(int mode, int vm, int dtype, int vi, const PolarArgs &a, uint32_t grid_mask, uint32_t grid_gen,
-                 hipStream_t s, int part = 0);
+                 hipStream_t s, int part = 0, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 int launch_prep(const PrepArgs &a, hipStream_t s);
 
 // Fixed device scratch of the allocation-free Polar entry point: its size,
@@ -136,8 +140,8 @@ __host__ __device__ inline uint64_t candidate_budget_words(uint64_t need, double
         return 0;
     const double q = 1.0 - p;
     const double P = (double)need;
-    const double c = P / p + 4.0 * sqrt(P * q) / p + 64.0;
-    return (uint64_t)(c / 64.0) + 1;
+    const double c = (P + 4.0 * sqrt(P * q)) / p + 64.0;
+    return (uint64_t)(c * (1.0 / 64.0)) + 1;
 }
 
 // Polar and P2: one accepted candidate per pair, p = pi/4.

@@ -66,6 +66,9 @@ def test_argument_errors_return_before_any_launch():
     assert L.nrng_batched(0, 0, None, None, None, None, None, None, None, 0, 1, None, None) == nb.NRNG_OK
     assert L.nrng_batched(1, 4, None, p, p, None, p, p, p, 100, 1, None, None) == nb.NRNG_EINVAL
     assert L.nrng_batched(1, 4, p, p, p, None, p, p, None, 100, 1, None, None) == nb.NRNG_EINVAL
+    # the timed exec needs both events
+    for e0, e1 in ((None, p), (p, None), (None, None)):
+        assert L.nrng_batched_exec_timed(0, 4, p, p, p, None, p, p, p, 1, None, None, e0, e1) == nb.NRNG_EINVAL
     # sizes beyond the supported range: 2^41 values for the rejection methods
     # and for a batch's output, 2^62 for the Box-Muller family
     assert L.nrng_polar(1, 0, (1 << 41) + 1, 0.0, 1.0, p, 1, None, None) == nb.NRNG_ERANGE

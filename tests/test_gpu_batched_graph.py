@@ -288,26 +288,40 @@ def test_polar_dev_under_torch_graph_capture():
 
 @pytest.mark.parametrize("method", [nb.NRNG_METHOD_B1, nb.NRNG_METHOD_POLAR])
 def test_exec_parts_equal_exec(method):
-    """The count half then the generate half of the exec sequence (the
-    timing hook) give exactly what exec gives; a part outside 0..2 is an
-    argument error."""
+    """The count half then the generate half of the exec sequence, and the
+    exec whose main kernel is timed by two events (the timing hooks), give
+    exactly what exec gives; the events bracket a positive time no longer
+    than the whole exec's; a part outside 0..2 is an argument error."""
     d = dev()
     cfg = small_config(61)
     D = to_dev(cfg, d)
     ns = len(cfg["n"])
+    stream = torch.cuda.current_stream()
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    for e in evs:
+        e.record(stream)   # torch creates its events on their first record
     outs = []
-    for parts in ((0,), (1, 2)):
+    for parts in ((0,), (1, 2), ("timed",)):
         out = torch.full((cfg["total"],), float("nan"), dtype=torch.float32, device=d)
         cons = torch.zeros(ns, dtype=torch.int64, device=d)
         case("exec parts", method, parts)
         nb.nrng_batched_plan(method, ns, D["n"], None, cfg["total"], nb.NRNG_F32, None, cons)
         for p in parts:
-            nb.nrng_batched_exec_part(p, method, ns, D["seed"], D["offset"], D["n"], None, D["mu"], D["sigma"],
-                                      out, nb.NRNG_F32, None, cons)
+            if p == "timed":
+                evs[0].record(stream)
+                nb.nrng_batched_exec_timed(method, ns, D["seed"], D["offset"], D["n"], None, D["mu"], D["sigma"],
+                                           out, nb.NRNG_F32, stream, cons, evs[1], evs[2])
+                evs[3].record(stream)
+            else:
+                nb.nrng_batched_exec_part(p, method, ns, D["seed"], D["offset"], D["n"], None, D["mu"],
+                                          D["sigma"], out, nb.NRNG_F32, None, cons)
         torch.cuda.synchronize()
         outs.append((out, u64(cons)))
-    assert torch.equal(outs[0][0], outs[1][0])
-    assert np.array_equal(outs[0][1], outs[1][1])
+    for o in outs[1:]:
+        assert torch.equal(outs[0][0], o[0])
+        assert np.array_equal(outs[0][1], o[1])
+    kernel_ms, exec_ms = evs[1].elapsed_time(evs[2]), evs[0].elapsed_time(evs[3])
+    assert 0.0 < kernel_ms <= exec_ms, (kernel_ms, exec_ms)
     with pytest.raises(nb.NrngError):
         nb.nrng_batched_exec_part(3, method, ns, D["seed"], D["offset"], D["n"], None, D["mu"], D["sigma"],
                                   outs[0][0], nb.NRNG_F32, None, None)
