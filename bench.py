@@ -17,6 +17,10 @@ graph-replayed repeated fill (64 x 2^28 Polar normals), methods P2 (Section
 4), B3 and B2 (Section 3) and Algorithm R (Section 5) on the same batched
 workload, and the CPU oracle timed on the host cores.
 
+The default 50 warm-up steps (about 60 ms of load) bring the GPU to its
+loaded state: with 3 the timed steps ran about 5% slower, and the step time
+levels off from about 20 warm-up steps on.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extras]
                        [--no-cpu] [--only b1|polar|p2|b3|ratio|b2]
 """
@@ -215,8 +219,8 @@ def median(xs):
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--nstreams", type=int, default=4096)
     ap.add_argument("--no-extras", action="store_true", help="skip the side measurements")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -271,54 +275,80 @@ def main() -> int:
     cons = {name: torch.zeros(ns, dtype=torch.int64, device=dev) for name, _ in methods}
     nb.nrng_reserve(total, ns)
 
-    # Each method: plan (set-up kernel), then exec.  Exec is launched as its
-    # two parts so that events can separate the kernels: for Polar, part 1 =
-    # the mask and scan kernels, part 2 = the generate kernel; for B1 part 1
-    # is empty and part 2 is the B1 kernel.  In the timed steps only part 2
-    # of each method is bracketed by events (2 per method: each timing event
-    # adds a little to the step); a breakdown pass after the timed region
-    # brackets every leg (4 events per method).
-    def step(evs=None, full=False):
+    # Each method: plan (set-up kernel), then exec.  Every event costs the
+    # stream a few microseconds (a marker, or the profiled dispatch of
+    # hipExtLaunchKernel), so the timed steps time one kernel only: the
+    # dominant one, the longest main kernel (B1's kernel; Polar's generate
+    # kernel) in the warm-up steps.  Its exec dispatches it with two events
+    # that take the dispatch's own start and end (nrng_batched_exec_timed).
+    # The warm-up steps and the breakdown pass after the timed region launch
+    # exec as its two parts with an event before and after each leg (plan,
+    # count, main kernel): for Polar part 1 = the mask and scan kernels, part
+    # 2 = the generate kernel; for B1 part 1 is empty.
+    def step(timed=-1, evs=None):
         for i, (name, m) in enumerate(methods):
-            if evs is not None and full:
-                evs[4 * i].record(stream)
+            nb.nrng_batched_plan(m, ns, D["n"], None, total, nb.NRNG_F32, stream, cons[name])
+            if i == timed:
+                nb.nrng_batched_exec_timed(m, ns, D["seed"], D["offset"], D["n"], None, D["mu"], D["sigma"],
+                                           outs[name], nb.NRNG_F32, stream, cons[name], evs[0], evs[1])
+            else:
+                nb.nrng_batched_exec(m, ns, D["seed"], D["offset"], D["n"], None, D["mu"], D["sigma"],
+                                     outs[name], nb.NRNG_F32, stream, cons[name])
+
+    def breakdown_step(evs):
+        for i, (name, m) in enumerate(methods):
+            evs[4 * i].record(stream)
             nb.nrng_batched_plan(m, ns, D["n"], None, total, nb.NRNG_F32, stream, cons[name])
             for part in (1, 2):
-                if evs is not None and (full or part == 2):
-                    evs[4 * i + part].record(stream)
+                evs[4 * i + part].record(stream)
                 nb.nrng_batched_exec_part(part, m, ns, D["seed"], D["offset"], D["n"], None, D["mu"], D["sigma"],
                                           outs[name], nb.NRNG_F32, stream, cons[name])
-            if evs is not None:
-                evs[4 * i + 3].record(stream)
+            evs[4 * i + 3].record(stream)
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
+    def new_events(k):
+        return [[torch.cuda.Event(enable_timing=True) for _ in range(k)] for _ in range(args.steps)]
+
+    def leg_ms(evs, i, a, b):
+        return sum(e[4 * i + a].elapsed_time(e[4 * i + b]) for e in evs) / len(evs)
+
     nev = 4 * len(methods)
-    events = [[torch.cuda.Event(enable_timing=True) for _ in range(nev)] for _ in range(args.steps)]
+    wu_events = [[torch.cuda.Event(enable_timing=True) for _ in range(nev)] for _ in range(args.warmup)]
+    for s in range(args.warmup):
+        breakdown_step(wu_events[s])
+    torch.cuda.synchronize()
+    # the dominant kernel, from the warm-up steps after the first
+    probe = len(methods) - 1
+    if args.warmup:
+        wu = wu_events[1:] if args.warmup > 1 else wu_events
+        probe = max(range(len(methods)), key=lambda i: leg_ms(wu, i, 2, 3))
+    events = new_events(2)
+    for evs in events:
+        for e in evs:
+            e.record(stream)   # torch creates an event on its first record
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(args.steps):
-        step(events[s])
+        step(probe, events[s])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     elapsed = t1 - t0
     normals = total * len(methods) * args.steps
     value = normals / elapsed
+    probe_ms = sum(e[0].elapsed_time(e[1]) for e in events) / args.steps
 
     # breakdown pass (not timed as steps): every leg between events
-    bd_events = [[torch.cuda.Event(enable_timing=True) for _ in range(nev)] for _ in range(args.steps)]
+    bd_events = new_events(nev)
     for s in range(args.steps):
-        step(bd_events[s], full=True)
+        breakdown_step(bd_events[s])
     torch.cuda.synchronize()
 
     pairs = int(sum((int(x) + 1) // 2 for x in cfg["n"]))
     per_kernel = {}
     for i, (name, _) in enumerate(methods):
-        def avg(evs, a, b):
-            return sum(evs[s][4 * i + a].elapsed_time(evs[s][4 * i + b]) for s in range(args.steps)) / args.steps
-        gen_ms = avg(events, 2, 3)                      # live, in the timed steps
-        plan_ms, count_ms = avg(bd_events, 0, 1), avg(bd_events, 1, 2)
+        # the dominant kernel live in the timed steps, the others from the
+        # breakdown pass
+        gen_ms = probe_ms if i == probe else leg_ms(bd_events, i, 2, 3)
+        plan_ms, count_ms = leg_ms(bd_events, i, 0, 1), leg_ms(bd_events, i, 1, 2)
         exec_ms = count_ms + gen_ms
         gbs = 4.0 * total / (exec_ms * 1e-3) / 1e9
         kid = nb.KERNEL_B1_BATCHED if name in ("b1", "b3", "b2") else nb.KERNEL_POLAR
@@ -326,7 +356,8 @@ def main() -> int:
         per_kernel[name] = {"plan_ms": round(plan_ms, 5), "exec_ms": round(exec_ms, 5),
                             "variant": {"wg": wg, "unroll": un, "grid_per_cu": gpc},
                             "normals_per_s": total / (exec_ms * 1e-3), "write_GBps": round(gbs, 1),
-                            "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)}
+                            "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
+                            "main_kernel_timed_in": "timed steps" if i == probe else "breakdown pass"}
         if name in ("polar", "p2", "ratio"):
             cand = int(u64sum(cons[name])) // 2       # candidates the method evaluates
             per_kernel[name]["count_ms"] = round(count_ms, 5)
@@ -350,19 +381,20 @@ def main() -> int:
                 "frac_valu_peak": round(ops / (exec_ms * 1e-3) / 1e12 / VALU_PEAK_TOPS, 4),
                 "generate_recomputed_ops_per_unit": recomputed_ops(name + "_generate", paired_share(cfg))}
 
-    # dominant kernel -> roofline (ALU-bound: VALU lane operations on the
-    # method's own work), with its HBM write rate beside (bytes: the output
-    # only, 4 B per FP32 normal) (among the part-2 kernels, whose durations
-    # come from the timed steps)
+    # dominant kernel (the one timed live, picked in the warm-up steps) ->
+    # roofline (ALU-bound: VALU lane operations on the method's own work),
+    # with its HBM write rate beside (bytes: the output only, 4 B per FP32
+    # normal)
     kern = {k: v for pk in per_kernel.values() for k, v in pk["alu"].items() if not k.endswith("_count")}
-    dom = max(kern, key=lambda k: kern[k]["ms"])
+    dom = [k for k in per_kernel[methods[probe][0]]["alu"] if not k.endswith("_count")][0]
     traffic = read_traffic("batched_%s_f32" % dom)
     wbytes = 4 * total
     roofline = {"bound": "alu", "achieved": kern[dom]["Tops_per_s"], "peak": VALU_PEAK_TOPS,
                 "unit": "Tlane-op/s", "frac": kern[dom]["frac_valu_peak"], "traffic": traffic,
                 "kernel": KERNEL_NAMES[dom], "ms_per_launch": kern[dom]["ms"],
                 "ops_per_unit": ALU_OPS[dom], "unit_of_work": ALU_UNIT[dom],
-                "timed_by": "HIP events around this kernel in every timed step, on its launch stream",
+                "timed_by": "two HIP events that take this kernel's own dispatch start and end "
+                            "(hipExtLaunchKernel) in every timed step, on its launch stream",
                 "algorithmic_write_bytes_per_launch": wbytes,
                 "hbm": {"achieved_GBps": round(wbytes / (kern[dom]["ms"] * 1e-3) / 1e9, 1), "peak_GBps": HBM_PEAK_GBS,
                         "frac": round(wbytes / (kern[dom]["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}}
