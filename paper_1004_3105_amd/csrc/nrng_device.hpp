@@ -834,6 +834,17 @@ __device__ __forceinline__ u32x16 scalar_load16(const void *p)
     return r;
 }
 
+// p[i] for a wave-uniform address, through the scalar unit: the constant
+// address space tells the compiler that the memory is not written while the
+// kernel runs (true of the stream tables, the tile table and the prefixes
+// an earlier kernel wrote), so the load goes to an SGPR and what is computed
+// from it stays scalar.
+template <typename T>
+__device__ __forceinline__ T ld_uniform(const T *p, uint64_t i)
+{
+    return ((const __attribute__((address_space(4))) T *)p)[i];
+}
+
 // Lane l's value of v (l wave-uniform).
 __device__ __forceinline__ uint64_t readlane64(uint64_t v, int l)
 {
