@@ -2,7 +2,9 @@
 
 For each kernel (B1 single stream, Polar, B1 batched) and output dtype it
 times every compiled (workgroup size, unroll) variant at a few persistent-
-grid caps on a representative workload, keeps the fastest, and writes the
+grid caps on a representative workload (single streams of 2^30 normals, the
+4096-stream batch), keeps the fastest (the current default unless another
+variant beats it by more than 1%), and writes the
 table to tune_<arch>.json and, in the plain-text form of the C ABI's
 nrng_tune_load, tune_<arch>.txt next to this file.  `apply()` loads such a
 table into the library.
@@ -59,6 +61,9 @@ def apply(path: str | None = None) -> bool:
     return True
 
 
+KEEP_MARGIN = 0.01
+
+
 def _time(torch, fn, reps):
     fn()
     torch.cuda.synchronize()
@@ -83,8 +88,8 @@ def tune(quick: bool = False, out_path: str | None = None, log=print) -> dict:
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     nb.nrng_init()
-    reps = 3 if quick else 7
-    n = 1 << (26 if quick else 28)
+    reps = 3 if quick else 9
+    n = 1 << (26 if quick else 30)
     cfg = synth.batched_streams(nstreams=1024 if quick else 4096)
     ns, total = len(cfg["n"]), cfg["total"]
     D = {k: torch.from_numpy(cfg[k].view(np.int64) if cfg[k].dtype == np.uint64 else cfg[k]).to(dev)
@@ -138,7 +143,14 @@ def tune(quick: bool = False, out_path: str | None = None, log=print) -> dict:
                     log("%-10s %-4s wg %4d unroll %2d grid/CU %d: %8.3f ms  %.3e normals/s" % (
                         KNAME[kernel], DNAME[dtype], wg, un, gpc, ms, work / (ms * 1e-3)))
             nb.nrng_tune_set(kernel, dtype, *saved)
+            # the fastest variant, except that the library's current default
+            # stays unless another is faster by more than KEEP_MARGIN (the
+            # spread of repeated timings), so that a re-tune does not move
+            # entries on noise
             best = min(results)
+            cur = [r for r in results if (r[1], r[2], r[3]) == tuple(saved)]
+            if cur and cur[0][0] <= best[0] * (1.0 + KEEP_MARGIN):
+                best = cur[0]
             entries.append({"kernel": KNAME[kernel], "dtype": DNAME[dtype], "wg": best[1], "unroll": best[2],
                             "grid_per_cu": best[3], "ms": round(best[0], 4)})
             del out

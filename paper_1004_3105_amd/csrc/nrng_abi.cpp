@@ -60,8 +60,8 @@ DevState g_dev[kMaxDev];
 // 2 = B1 batched; dtype order F64, F32, BF16, F16; entries are {variant
 // index, grid cap per CU (0 = occupancy)}.
 Tune g_tune[3][4] = {
-    {{2, 0}, {4, 0}, {4, 0}, {4, 0}},
-    {{1, 0}, {1, 0}, {1, 0}, {1, 0}},
+    {{4, 4}, {4, 0}, {4, 0}, {4, 0}},
+    {{3, 4}, {1, 0}, {1, 0}, {1, 0}},
     {{2, 0}, {2, 0}, {1, 0}, {1, 0}},
 };
 

@@ -286,7 +286,8 @@ def test_polar_dev_under_torch_graph_capture():
         del y
 
 
-@pytest.mark.parametrize("method", [nb.NRNG_METHOD_B1, nb.NRNG_METHOD_POLAR])
+@pytest.mark.parametrize("method", [nb.NRNG_METHOD_B1, nb.NRNG_METHOD_POLAR, nb.NRNG_METHOD_P2,
+                                    nb.NRNG_METHOD_B3, nb.NRNG_METHOD_R, nb.NRNG_METHOD_B2])
 def test_exec_parts_equal_exec(method):
     """The count half then the generate half of the exec sequence, and the
     exec whose main kernel is timed by two events (the timing hooks), give
