@@ -695,6 +695,7 @@ int nrng_batched_plan(int method, uint32_t nstreams, const uint64_t *d_n, const 
         b1_variants(&v);
         const uint64_t ppl = (dtype == NRNG_F64) ? 1 : (dtype == NRNG_F32 ? 2 : 4);
         p.unit = (uint64_t)v[tu.vi].wg * v[tu.vi].unroll * ppl;
+        p.esize = (uint32_t)(16 / (2 * ppl));
     } else {
         const uint64_t U = polar_tile_words(tu.vi);
         const uint64_t wb = batched_word_bound(method, out_len, nstreams);

@@ -74,9 +74,12 @@ __global__ __launch_bounds__(1024) void prep_kernel(PrepArgs a)
 #pragma unroll
         for (uint32_t i = 0; i < P; ++i) {
             valid[i] = j0 + i < NS && n[i] <= a.out_len && off[i] <= a.out_len - n[i];
-            // the candidate budget of a rejection stream, computed once
+            // the candidate budget of a rejection stream, computed once; a
+            // Box-Muller stream's tiles cover its n elements after the line
+            // shift
             wd[i] = (!bm_family && valid[i]) ? method_budget_words(a.method, n[i]) : 0;
-            tl[i] = valid[i] ? tiles_in(bm_family ? (n[i] + 1) / 2 : wd[i]) : 0;
+            const uint64_t sh = a.esize ? line_shift_elems(off[i], a.esize) : 0;
+            tl[i] = !valid[i] ? 0 : (bm_family ? (n[i] ? tiles_in((n[i] + sh + 1) / 2) : 0) : tiles_in(wd[i]));
             tsum = sat_add(tsum, tl[i]);
             vsum = sat_add(vsum, valid[i] ? n[i] : 0);
         }

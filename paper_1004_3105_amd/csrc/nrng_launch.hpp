@@ -73,8 +73,20 @@ struct B1Args {
     const double *mus, *sigmas;
 };
 
+// Batched Box-Muller family: a stream's output is cut into segments in
+// virtual elements x = (stream element) + sh, with sh the even shift below one
+// 128-byte line that puts x = 0 (and every pass, 64 groups of 16 bytes) on a
+// line boundary of the output when the buffer itself is line-aligned.  The
+// set-up kernel counts the tiles of a stream over n + sh elements.
+constexpr uint64_t kLineBytes = 128;
+__host__ __device__ inline uint64_t line_shift_elems(uint64_t off, uint64_t esize)
+{
+    return (off & (kLineBytes / esize - 1)) & ~1ull;
+}
+
 struct PrepArgs {
     int method;                      // 0 = B1, 1 = Polar, 2 = P2, 3 = B3, 4 = Algorithm R, 5 = B2
+    uint32_t esize;                  // bytes per output element (Box-Muller family: the line shift)
     uint32_t nstreams;
     const uint64_t *ns, *out_off;    // out_off nullable (packed)
     uint64_t out_len;
