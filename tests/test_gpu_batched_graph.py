@@ -7,7 +7,7 @@ import torch
 
 import oracle as O
 import synth
-from gpu_util import TDT, assert_close, case, dev, host, run, u64
+from gpu_util import NAME, TDT, assert_close, case, dev, host, run, u64
 from paper_1004_3105_amd import binding as nb
 
 pytestmark = pytest.mark.gpu
@@ -153,7 +153,7 @@ def test_batched_explicit_offsets_and_invalid_streams(method):
         written[o0:o0 + nj] = True
     # gaps and the skipped stream's range are untouched (except where a
     # valid stream overlaps them)
-    assert torch.all(out[~written] == -777.0)
+    assert torch.all(out[~written] == -512.0)
 
 
 def test_batched_overflowing_total_is_rejected_on_device():
@@ -365,3 +365,52 @@ def test_batched_plan_and_exec_under_torch_graph_capture(method):
         y = torch.ones(1 << 16, device=d).sum()           # eager work between replays
         torch.cuda.synchronize()
         del y
+
+
+@pytest.mark.parametrize("method", [nb.NRNG_METHOD_B1, nb.NRNG_METHOD_B3, nb.NRNG_METHOD_B2])
+@pytest.mark.parametrize("dtype", [nb.NRNG_F64, nb.NRNG_F32, nb.NRNG_BF16, nb.NRNG_F16])
+def test_batched_box_muller_every_place_in_a_line(method, dtype):
+    """The batched Box-Muller family starts each stream's passes on a
+    128-byte line of the output (its first segment begins up to a line
+    before the stream and stores nothing there).  Streams whose first
+    element takes every place in a line, with lengths around the pass and
+    segment sizes, equal the single-stream calls bit for bit, and nothing
+    outside the streams is written (gaps of 1 to 3 elements stay as they
+    were)."""
+    d = dev()
+    esize = {nb.NRNG_F64: 8, nb.NRNG_F32: 4, nb.NRNG_BF16: 2, nb.NRNG_F16: 2}[dtype]
+    line = 128 // esize
+    lens = [1, 2, 3, 5, 31, 33, 64, 255, 257, 1023, 1025, 2049, 4095, 4097, 9001]
+    ns = 2 * line
+    r = synth.rng(31)
+    n = np.array([lens[j % len(lens)] for j in range(ns)], dtype=np.uint64)
+    off = np.zeros(ns, dtype=np.uint64)
+    pos = 0
+    for j in range(ns):
+        # stream j starts at place j mod line of a line (the buffer is line-aligned)
+        pos += (j % line - pos) % line or line
+        off[j] = pos
+        pos += int(n[j]) + int(r.integers(1, 4))
+    out_len = pos
+    seeds = r.integers(0, 1 << 63, ns, dtype=np.uint64)
+    offs = r.integers(0, 1 << 40, ns, dtype=np.uint64)
+    mus = r.uniform(-3.0, 3.0, ns)
+    sigmas = r.uniform(0.5, 2.0, ns)
+    D = {"seed": torch.from_numpy(seeds.view(np.int64)).to(d), "offset": torch.from_numpy(offs.view(np.int64)).to(d),
+         "n": torch.from_numpy(n.view(np.int64)).to(d), "mu": torch.from_numpy(mus).to(d),
+         "sigma": torch.from_numpy(sigmas).to(d), "off": torch.from_numpy(off.view(np.int64)).to(d)}
+    out = torch.full((out_len,), -512.0, dtype=TDT[dtype], device=d)
+    assert out.data_ptr() % 128 == 0
+    cons = torch.zeros(ns, dtype=torch.int64, device=d)
+    case("batched Box-Muller line places", method, NAME[dtype])
+    nb.nrng_batched(method, ns, D["seed"], D["offset"], D["n"], D["off"], D["mu"], D["sigma"], out, out_len, dtype,
+                    None, cons)
+    torch.cuda.synchronize()
+    name = {nb.NRNG_METHOD_B1: "b1", nb.NRNG_METHOD_B3: "b3", nb.NRNG_METHOD_B2: "b2"}[method]
+    written = torch.zeros(out_len, dtype=torch.bool, device=d)
+    for j in range(ns):
+        o0, nj = int(off[j]), int(n[j])
+        single = run(name, int(seeds[j]), int(offs[j]), nj, dtype, float(mus[j]), float(sigmas[j]))
+        assert torch.equal(out[o0:o0 + nj], single), (j, o0 % line, nj)
+        written[o0:o0 + nj] = True
+    assert torch.all(out[~written] == -512.0)
