@@ -14,8 +14,9 @@ int polar_variants(const Variant **v) { *v = kPolarVariants; return kNPolar; }
 // ---------------------------------------------------------------------------
 // Batched set-up (one workgroup of 1024 threads): per stream, the output
 // offset (packed prefix sum when none is given), the range check against
-// out_len and the tile count; then the exclusive prefix of the tile counts
-// (the tile table) and the initial consumed values.
+// out_len and the tile count (Box-Muller family: over n plus the stream's
+// line shift, as the batched kernel cuts it); then the exclusive prefix of
+// the tile counts (the tile table) and the initial consumed values.
 //
 // Streams go in chunks of 1024 x kPrepPer; thread t takes kPrepPer
 // consecutive streams of a chunk, so its loads are issued together, and the
