@@ -153,7 +153,7 @@ def test_batched_explicit_offsets_and_invalid_streams(method):
         written[o0:o0 + nj] = True
     # gaps and the skipped stream's range are untouched (except where a
     # valid stream overlaps them)
-    assert torch.all(out[~written] == -512.0)
+    assert torch.all(out[~written] == -777.0)
 
 
 def test_batched_overflowing_total_is_rejected_on_device():
