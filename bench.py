@@ -4,10 +4,14 @@
 One step = the batched workload (4096 streams, lengths log-uniform on
 [1e2, 1e6], per-stream mu, sigma and seed; about 4.45e8 normals per method)
 turned into FP32 normals by Box-Muller (Algorithm B1) AND by the Polar method
-(Algorithm P), each as one tile-table set-up kernel plus one persistent
-kernel, through the C ABI.  The printed `value` is the whole step's
-throughput in normals per second (both methods' normals over the step time),
-with every input resident in GPU memory before timing starts.
+(Algorithm P), through the C ABI: for each, one tile-table set-up kernel,
+then B1's persistent kernel, or Polar's mask, chunk-scan and generate
+kernels.  The printed `value` is the whole step's throughput in normals per
+second (both methods' normals over the step time), with every input resident
+in GPU memory before timing starts.  One kernel is timed inside the timed
+steps, by the two events of its own dispatch: the dominant one (the longest
+main kernel of the warm-up steps); a breakdown pass after the timed steps
+times the other legs.
 
 Alongside, outside the timed region: the measured store-only ceiling (best
 of a sweep over plain and nontemporal stores and launch shapes), the
