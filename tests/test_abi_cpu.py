@@ -125,6 +125,20 @@ def test_binding_checks_tensor_sizes_before_calling():
         nb.nrng_test_polar_xy(torch.empty(3, dtype=torch.int32), 2, 0.0, 1.0, small, nb.NRNG_F32, None, None, 0)
 
 
+def test_timed_exec_binding_needs_created_events():
+    """The timed exec takes hipEvent_t handles: an int handle passes through,
+    and anything without a created event (None, a plain object) is refused
+    before the call; a null handle is the library's argument error."""
+    assert nb._event(0x1234) == 0x1234
+    for bad in (None, object()):
+        with pytest.raises(ValueError):
+            nb._event(bad)
+    p = 0x1000
+    with pytest.raises(nb.NrngError) as e:
+        nb.nrng_batched_exec_timed(nb.NRNG_METHOD_B1, 4, p, p, p, None, p, p, p, nb.NRNG_F32, 0, None, 0, p)
+    assert e.value.status == nb.NRNG_EINVAL
+
+
 def test_b2_kernel_coefficients_equal_the_oracles():
     """Method B2's coefficients are derived twice, independently: by the
     kernels' generator (mpmath quadrature of the Chebyshev coefficients,
