@@ -293,7 +293,7 @@ def main() -> int:
         for i, (name, m) in enumerate(methods):
             nb.nrng_batched_plan(m, ns, D["n"], None, total, nb.NRNG_F32, stream, cons[name])
             if i == timed:
-                nb.nrng_batched_exec_timed(m, ns, D["seed"], D["offset"], D["n"], None, D["mu"], D["sigma"],
+                nb.nrng_batched_exec_timed(0, m, ns, D["seed"], D["offset"], D["n"], None, D["mu"], D["sigma"],
                                            outs[name], nb.NRNG_F32, stream, cons[name], evs[0], evs[1])
             else:
                 nb.nrng_batched_exec(m, ns, D["seed"], D["offset"], D["n"], None, D["mu"], D["sigma"],

@@ -289,20 +289,26 @@ int nrng_batched(int method, uint32_t nstreams, const uint64_t *d_seed, const ui
  * nrng_batched_plan builds the tile table of the batch in the device
  * workspace (one small kernel; d_consumed as in nrng_batched, written for
  * skipped and empty streams and for every B1 stream); nrng_batched_exec runs
- * the persistent kernel over the most recent plan of this device.  exec
- * returns NRNG_EINVAL unless the latest plan was made for the same method,
- * dtype, launch variant, stream count and layout (packed or not); d_n and
- * d_out_off must hold the values the plan saw.  A plan stays valid until the
- * next plan or batched call on the device.  nrng_batched(...) is
- * plan + exec.
+ * the persistent kernel over the most recent plan of the method's family on
+ * this device (families below).  exec returns NRNG_EINVAL unless that plan
+ * was made for the same method, dtype, launch variant, stream count and
+ * layout (packed or not); d_n and d_out_off must hold the values the plan
+ * saw.  A plan stays valid until the next plan or batched call of its
+ * family on the device.  nrng_batched(...) is plan + exec.
  * nrng_batched_exec_part runs one half of exec's launch sequence, for timing
  * and profiling the kernels separately: part 1 = the Polar (or P2) mask and
  * scan kernels (nothing for B1 and B3), part 2 = the generate kernel (the B1 or B3
  * kernel for B1), part 0 = both (identical to nrng_batched_exec).  Part 2
  * reads what part 1 of the same plan left in the workspace, so it must
- * follow it on the same stream with no other Polar call in between.  Same
- * arguments and errors as nrng_batched_exec, plus NRNG_EINVAL for a part
- * outside 0..2. */
+ * follow it (on the same stream, or ordered after it by an event) with no
+ * other Polar call in between.  Same arguments and errors as
+ * nrng_batched_exec, plus NRNG_EINVAL for a part outside 0..2.
+ *
+ * The two method families keep separate tables: the Box-Muller family (B1,
+ * B3, B2) and the rejection family (Polar, P2, R; these also share the
+ * candidate workspace).  A plan stays valid until the next plan or batched
+ * call of its own family, so a batch of each family may be planned and run
+ * at the same time on two streams; calls of one family must not overlap. */
 int nrng_batched_plan(int method, uint32_t nstreams, const uint64_t *d_n, const uint64_t *d_out_off,
                       uint64_t out_len, int dtype, void *stream, uint64_t *d_consumed);
 int nrng_batched_exec(int method, uint32_t nstreams, const uint64_t *d_seed, const uint64_t *d_offset,
@@ -313,21 +319,23 @@ int nrng_batched_exec_part(int part, int method, uint32_t nstreams, const uint64
                            const double *d_mu, const double *d_sigma, void *out, int dtype, void *stream,
                            uint64_t *d_consumed);
 
-/* nrng_batched_exec with its main kernel timed: the same launches, results
- * and errors, except that the main kernel (the Box-Muller family's batched
- * kernel, or the Polar, P2 or R generate kernel) is dispatched with
+/* nrng_batched_exec_part with its main kernel timed: the same launches,
+ * results and errors, except that the main kernel (the Box-Muller family's
+ * batched kernel, or the Polar, P2 or R generate kernel) is dispatched with
  * hipExtLaunchKernel so that ev_start and ev_stop record that dispatch's own
- * start and end.  No marker is added to the stream, so timing a step this
- * way does not lengthen it, and hipEventElapsedTime(ev_start, ev_stop) is
- * the kernel's duration alone.
+ * start and end.  No marker is added to the stream, and
+ * hipEventElapsedTime(ev_start, ev_stop) is the kernel's duration alone.
+ *   part               0 (the whole exec) or 2 (the main kernel); part 1
+ *                      has no main kernel (NRNG_EINVAL)
  *   ev_start, ev_stop  hipEvent_t handles created by the caller (with
  *                      timing enabled) on the stream's device; both are
  *                      required (NRNG_EINVAL if either is NULL).
  * The events are not recorded when nothing is launched (nstreams 0, or an
  * error return). */
-int nrng_batched_exec_timed(int method, uint32_t nstreams, const uint64_t *d_seed, const uint64_t *d_offset,
-                            const uint64_t *d_n, const uint64_t *d_out_off, const double *d_mu, const double *d_sigma,
-                            void *out, int dtype, void *stream, uint64_t *d_consumed, void *ev_start, void *ev_stop);
+int nrng_batched_exec_timed(int part, int method, uint32_t nstreams, const uint64_t *d_seed,
+                            const uint64_t *d_offset, const uint64_t *d_n, const uint64_t *d_out_off,
+                            const double *d_mu, const double *d_sigma, void *out, int dtype, void *stream,
+                            uint64_t *d_consumed, void *ev_start, void *ev_stop);
 
 /* ------------------------------------------------------------------------
  * Repeated fills through a HIP graph: capture one nrng_polar_dev launch

@@ -43,7 +43,8 @@ _SIGS = {
     "nrng_batched_plan": (_i32, [_i32, _u32, _vp, _vp, _u64, _i32, _vp, _vp]),
     "nrng_batched_exec": (_i32, [_i32, _u32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp]),
     "nrng_batched_exec_part": (_i32, [_i32, _i32, _u32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp]),
-    "nrng_batched_exec_timed": (_i32, [_i32, _u32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp]),
+    "nrng_batched_exec_timed": (_i32, [_i32, _i32, _u32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp,
+                                       _vp]),
     "nrng_fillgraph_create": (_i32, [_u64, _vp, _u64, _f64, _f64, _vp, _i32, _vp, ctypes.POINTER(_vp)]),
     "nrng_fillgraph_launch": (_i32, [_vp, _vp]),
     "nrng_fillgraph_destroy": (_i32, [_vp]),
@@ -259,15 +260,15 @@ def _event(e):
     return h
 
 
-def nrng_batched_exec_timed(method, nstreams, d_seed, d_offset, d_n, d_out_off, d_mu, d_sigma, out, dtype,
+def nrng_batched_exec_timed(part, method, nstreams, d_seed, d_offset, d_n, d_out_off, d_mu, d_sigma, out, dtype,
                             stream, d_consumed, ev_start, ev_stop) -> None:
     for t, nm in ((d_seed, "d_seed"), (d_offset, "d_offset"), (d_n, "d_n"), (d_out_off, "d_out_off"),
                   (d_mu, "d_mu"), (d_sigma, "d_sigma"), (d_consumed, "d_consumed")):
         _need(t, 8 * nstreams, "nrng_batched_exec_timed " + nm)
     _check("nrng_batched_exec_timed",
-           lib().nrng_batched_exec_timed(method, nstreams, _ptr(d_seed), _ptr(d_offset), _ptr(d_n), _ptr(d_out_off),
-                                         _ptr(d_mu), _ptr(d_sigma), _ptr(out), dtype, _stream(stream),
-                                         _ptr(d_consumed), _event(ev_start), _event(ev_stop)))
+           lib().nrng_batched_exec_timed(part, method, nstreams, _ptr(d_seed), _ptr(d_offset), _ptr(d_n),
+                                         _ptr(d_out_off), _ptr(d_mu), _ptr(d_sigma), _ptr(out), dtype,
+                                         _stream(stream), _ptr(d_consumed), _event(ev_start), _event(ev_stop)))
 
 
 def nrng_fillgraph_create(seed, d_cursor, n, mu, sigma, out, dtype, stream) -> int:

@@ -33,18 +33,22 @@ struct DevState {
     uint32_t *csum = nullptr;
     uint64_t *cpfx = nullptr;
     uint64_t *misc = nullptr;
-    // batched tables
-    uint64_t *tile_start = nullptr;
-    uint64_t *stream_words = nullptr;
-    uint64_t *packed_off = nullptr;
-    uint64_t stream_cap = 0;
+    // batched tables, one set per method family ([0] B1, B3 and B2; [1]
+    // Polar, P2 and R), so that a batch of each family can be in flight at
+    // once: the tile table, the candidate budgets (rejection family) and the
+    // packed offsets, with the plan they hold (from nrng_batched_plan)
+    struct Plan {
+        uint64_t *tile_start = nullptr;
+        uint64_t *stream_words = nullptr;
+        uint64_t *packed_off = nullptr;
+        uint64_t cap = 0;
+        int method = -1, dtype = -1, vi = -1;
+        uint32_t nstreams = 0;
+        bool packed = false;
+    } plan[2];
     int occ_polar[3][4][4][8] = {};  // generate kernel: [value method][mode][dtype][variant], 0 = not queried
     int occ_mask[3][4][8] = {};      // mask kernel: [value method][mode][variant]
     int occ_b1[3][2][4][8] = {};     // [B1 / B3 / B2][batched][dtype][variant]
-    // the tile table currently in the workspace (from nrng_batched_plan)
-    int plan_method = -1, plan_dtype = -1, plan_vi = -1;
-    uint32_t plan_nstreams = 0;
-    bool plan_packed = false;
 };
 
 struct Tune {
@@ -167,26 +171,30 @@ int ensure_polar_ws(DevState &d, uint64_t tiles, uint64_t words, hipStream_t s)
     return NRNG_OK;
 }
 
-int ensure_streams(DevState &d, uint64_t nstreams, hipStream_t s)
+// The batched tables of method family fam (0 = Box-Muller, 1 = rejection)
+// for at least nstreams streams.
+int ensure_streams(DevState &d, int fam, uint64_t nstreams, hipStream_t s)
 {
-    if (nstreams <= d.stream_cap)
+    DevState::Plan &pl = d.plan[fam];
+    if (nstreams <= pl.cap)
         return NRNG_OK;
     if (capturing(s))
         return NRNG_ECAPTURE;
     uint64_t cap = nstreams + nstreams / 4 + 256;
     if (hipDeviceSynchronize() != hipSuccess)
         return NRNG_EHIP;
-    for (uint64_t **p : {&d.tile_start, &d.stream_words, &d.packed_off}) {
+    for (uint64_t **p : {&pl.tile_start, &pl.stream_words, &pl.packed_off}) {
         if (*p)
             (void)hipFree(*p);
         *p = nullptr;
     }
-    d.stream_cap = 0;
-    if (hipMalloc(&d.tile_start, (cap + 1) * sizeof(uint64_t)) != hipSuccess ||
-        hipMalloc(&d.stream_words, (cap + 1) * sizeof(uint64_t)) != hipSuccess ||
-        hipMalloc(&d.packed_off, cap * sizeof(uint64_t)) != hipSuccess)
+    pl.cap = 0;
+    pl.method = -1;
+    if (hipMalloc(&pl.tile_start, (cap + 1) * sizeof(uint64_t)) != hipSuccess ||
+        (fam == 1 && hipMalloc(&pl.stream_words, (cap + 1) * sizeof(uint64_t)) != hipSuccess) ||
+        hipMalloc(&pl.packed_off, cap * sizeof(uint64_t)) != hipSuccess)
         return NRNG_ENOMEM;
-    d.stream_cap = cap;
+    pl.cap = cap;
     return NRNG_OK;
 }
 
@@ -544,8 +552,9 @@ int nrng_reserve(uint64_t max_n, uint32_t max_streams)
     }
     if ((rc = ensure_polar_ws(*d, tiles, words, nullptr)))
         return rc;
-    if (max_streams && (rc = ensure_streams(*d, max_streams, nullptr)))
-        return rc;
+    for (int fam = 0; fam < 2; ++fam)
+        if (max_streams && (rc = ensure_streams(*d, fam, max_streams, nullptr)))
+            return rc;
     return NRNG_OK;
 }
 
@@ -676,8 +685,10 @@ int nrng_batched_plan(int method, uint32_t nstreams, const uint64_t *d_n, const 
     int rc = get_dev(&d);
     if (rc)
         return rc;
-    if ((rc = ensure_streams(*d, nstreams, s)))
+    const int fam = method_bm(method) ? 0 : 1;
+    if ((rc = ensure_streams(*d, fam, nstreams, s)))
         return rc;
+    DevState::Plan &pl = d->plan[fam];
     const int kid = method_bm(method) ? 2 : 1;
     const Tune tu = g_tune[kid][dtype];
     PrepArgs p;
@@ -687,8 +698,8 @@ int nrng_batched_plan(int method, uint32_t nstreams, const uint64_t *d_n, const 
     p.ns = d_n;
     p.out_off = d_out_off;
     p.out_len = out_len;
-    p.tile_start = d->tile_start;
-    p.packed_off = d->packed_off;
+    p.tile_start = pl.tile_start;
+    p.packed_off = pl.packed_off;
     p.consumed = d_consumed;
     if (method_bm(method)) {
         const Variant *v;
@@ -708,15 +719,15 @@ int nrng_batched_plan(int method, uint32_t nstreams, const uint64_t *d_n, const 
         p.unit = U;
         p.word_cap = d->word_cap;
         p.tile_cap = d->tile_cap;
-        p.stream_words = d->stream_words;
+        p.stream_words = pl.stream_words;
     }
     if ((rc = hip_status(launch_prep(p, s))))
         return rc;
-    d->plan_method = method;
-    d->plan_dtype = dtype;
-    d->plan_vi = tu.vi;
-    d->plan_nstreams = nstreams;
-    d->plan_packed = d_out_off == nullptr;
+    pl.method = method;
+    pl.dtype = dtype;
+    pl.vi = tu.vi;
+    pl.nstreams = nstreams;
+    pl.packed = d_out_off == nullptr;
     return NRNG_OK;
 }
 
@@ -751,22 +762,23 @@ static int batched_exec(int part, int method, uint32_t nstreams, const uint64_t 
     int rc = get_dev(&d);
     if (rc)
         return rc;
-    // the tile table must come from a plan for this method, dtype, variant,
-    // stream count and layout
+    // the tile table must come from a plan of the method's family for this
+    // method, dtype, variant, stream count and layout
     const int kid = method_bm(method) ? 2 : 1;
     const Tune tu = g_tune[kid][dtype];
-    if (d->plan_method != method || d->plan_dtype != dtype || d->plan_vi != tu.vi ||
-        d->plan_nstreams != nstreams || d->plan_packed != (d_out_off == nullptr))
+    const DevState::Plan &pl = d->plan[method_bm(method) ? 0 : 1];
+    if (pl.method != method || pl.dtype != dtype || pl.vi != tu.vi || pl.nstreams != nstreams ||
+        pl.packed != (d_out_off == nullptr))
         return NRNG_EINVAL;
     if (!out)
         return NRNG_EINVAL;
-    const uint64_t *off = d_out_off ? d_out_off : d->packed_off;
+    const uint64_t *off = d_out_off ? d_out_off : pl.packed_off;
     if (method_bm(method)) {
         B1Args a;
         std::memset(&a, 0, sizeof(a));
         a.out = out;
         a.nstreams = nstreams;
-        a.tile_start = d->tile_start;
+        a.tile_start = pl.tile_start;
         a.seeds = d_seed;
         a.offsets = d_offset;
         a.ns = d_n;
@@ -784,8 +796,8 @@ static int batched_exec(int part, int method, uint32_t nstreams, const uint64_t 
     a.sigma = 1.0;
     a.out = out;
     a.nstreams = nstreams;
-    a.tile_start = d->tile_start;
-    a.stream_words = d->stream_words;
+    a.tile_start = pl.tile_start;
+    a.stream_words = pl.stream_words;
     a.seeds = d_seed;
     a.offsets = d_offset;
     a.ns = d_n;
@@ -809,13 +821,14 @@ int nrng_batched_exec_part(int part, int method, uint32_t nstreams, const uint64
                         d_consumed, nullptr, nullptr);
 }
 
-int nrng_batched_exec_timed(int method, uint32_t nstreams, const uint64_t *d_seed, const uint64_t *d_offset,
-                            const uint64_t *d_n, const uint64_t *d_out_off, const double *d_mu, const double *d_sigma,
-                            void *out, int dtype, void *stream, uint64_t *d_consumed, void *ev_start, void *ev_stop)
+int nrng_batched_exec_timed(int part, int method, uint32_t nstreams, const uint64_t *d_seed,
+                            const uint64_t *d_offset, const uint64_t *d_n, const uint64_t *d_out_off,
+                            const double *d_mu, const double *d_sigma, void *out, int dtype, void *stream,
+                            uint64_t *d_consumed, void *ev_start, void *ev_stop)
 {
-    if (!ev_start || !ev_stop)
+    if (!ev_start || !ev_stop || (part != 0 && part != 2))
         return NRNG_EINVAL;
-    return batched_exec(0, method, nstreams, d_seed, d_offset, d_n, d_out_off, d_mu, d_sigma, out, dtype, stream,
+    return batched_exec(part, method, nstreams, d_seed, d_offset, d_n, d_out_off, d_mu, d_sigma, out, dtype, stream,
                         d_consumed, (hipEvent_t)ev_start, (hipEvent_t)ev_stop);
 }
 

@@ -68,7 +68,10 @@ def test_argument_errors_return_before_any_launch():
     assert L.nrng_batched(1, 4, p, p, p, None, p, p, None, 100, 1, None, None) == nb.NRNG_EINVAL
     # the timed exec needs both events
     for e0, e1 in ((None, p), (p, None), (None, None)):
-        assert L.nrng_batched_exec_timed(0, 4, p, p, p, None, p, p, p, 1, None, None, e0, e1) == nb.NRNG_EINVAL
+        assert L.nrng_batched_exec_timed(0, 0, 4, p, p, p, None, p, p, p, 1, None, None, e0, e1) == nb.NRNG_EINVAL
+    # ... and a part with a main kernel (0 or 2)
+    for part in (-1, 1, 3):
+        assert L.nrng_batched_exec_timed(part, 0, 4, p, p, p, None, p, p, p, 1, None, None, p, p) == nb.NRNG_EINVAL
     # sizes beyond the supported range: 2^41 values for the rejection methods
     # and for a batch's output, 2^62 for the Box-Muller family
     assert L.nrng_polar(1, 0, (1 << 41) + 1, 0.0, 1.0, p, 1, None, None) == nb.NRNG_ERANGE
@@ -135,7 +138,7 @@ def test_timed_exec_binding_needs_created_events():
             nb._event(bad)
     p = 0x1000
     with pytest.raises(nb.NrngError) as e:
-        nb.nrng_batched_exec_timed(nb.NRNG_METHOD_B1, 4, p, p, p, None, p, p, p, nb.NRNG_F32, 0, None, 0, p)
+        nb.nrng_batched_exec_timed(0, nb.NRNG_METHOD_B1, 4, p, p, p, None, p, p, p, nb.NRNG_F32, 0, None, 0, p)
     assert e.value.status == nb.NRNG_EINVAL
 
 

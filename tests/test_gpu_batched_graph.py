@@ -310,7 +310,7 @@ def test_exec_parts_equal_exec(method):
         for p in parts:
             if p == "timed":
                 evs[0].record(stream)
-                nb.nrng_batched_exec_timed(method, ns, D["seed"], D["offset"], D["n"], None, D["mu"], D["sigma"],
+                nb.nrng_batched_exec_timed(0, method, ns, D["seed"], D["offset"], D["n"], None, D["mu"], D["sigma"],
                                            out, nb.NRNG_F32, stream, cons, evs[1], evs[2])
                 evs[3].record(stream)
             else:
@@ -414,3 +414,58 @@ def test_batched_box_muller_every_place_in_a_line(method, dtype):
         assert torch.equal(out[o0:o0 + nj], single), (j, o0 % line, nj)
         written[o0:o0 + nj] = True
     assert torch.all(out[~written] == -512.0)
+
+
+@pytest.mark.parametrize("pair", [(nb.NRNG_METHOD_B1, nb.NRNG_METHOD_POLAR), (nb.NRNG_METHOD_B3, nb.NRNG_METHOD_R),
+                                  (nb.NRNG_METHOD_B2, nb.NRNG_METHOD_P2)])
+def test_two_families_planned_together_and_run_side_by_side(pair):
+    """The Box-Muller family and the rejection family keep separate batched
+    tables: both plans are made first, then the two execs run at the same
+    time on two streams (the rejection exec split in its two parts around a
+    join, as the benchmark does); every output and consumed count equals the
+    calls made one after the other on one stream."""
+    d = dev()
+    cfg = small_config(211)
+    D = to_dev(cfg, d)
+    ns, total = len(cfg["n"]), cfg["total"]
+    nb.nrng_reserve(total, ns)
+    main = torch.cuda.current_stream()
+    side = torch.cuda.Stream()
+    ref = {}
+    for m in pair:
+        out = torch.full((total,), float("nan"), dtype=torch.float32, device=d)
+        cons = torch.zeros(ns, dtype=torch.int64, device=d)
+        case("family reference", m)
+        nb.nrng_batched(m, ns, D["seed"], D["offset"], D["n"], None, D["mu"], D["sigma"], out, total, nb.NRNG_F32,
+                        main, cons)
+        torch.cuda.synchronize()
+        ref[m] = (out, u64(cons))
+    bm, rj = pair
+    got = {m: (torch.full((total,), float("nan"), dtype=torch.float32, device=d),
+               torch.zeros(ns, dtype=torch.int64, device=d)) for m in pair}
+    for rep in range(3):
+        case("families side by side", pair, rep)
+        fork, join = torch.cuda.Event(), torch.cuda.Event()
+        fork.record(main)
+        side.wait_event(fork)
+        nb.nrng_batched_plan(bm, ns, D["n"], None, total, nb.NRNG_F32, main, got[bm][1])
+        nb.nrng_batched_plan(rj, ns, D["n"], None, total, nb.NRNG_F32, side, got[rj][1])
+        nb.nrng_batched_exec(bm, ns, D["seed"], D["offset"], D["n"], None, D["mu"], D["sigma"], got[bm][0],
+                             nb.NRNG_F32, main, got[bm][1])
+        nb.nrng_batched_exec_part(1, rj, ns, D["seed"], D["offset"], D["n"], None, D["mu"], D["sigma"], got[rj][0],
+                                  nb.NRNG_F32, side, got[rj][1])
+        join.record(side)
+        main.wait_event(join)
+        nb.nrng_batched_exec_part(2, rj, ns, D["seed"], D["offset"], D["n"], None, D["mu"], D["sigma"], got[rj][0],
+                                  nb.NRNG_F32, main, got[rj][1])
+        torch.cuda.synchronize()
+        for m in pair:
+            assert torch.equal(got[m][0], ref[m][0]), (m, rep)
+            assert np.array_equal(u64(got[m][1]), ref[m][1]), (m, rep)
+    # a plan of one family leaves the other family's plan in place
+    nb.nrng_batched_plan(rj, ns, D["n"], None, total, nb.NRNG_F32, main, got[rj][1])
+    nb.nrng_batched_plan(bm, ns, D["n"], None, total, nb.NRNG_F32, main, got[bm][1])
+    nb.nrng_batched_exec(rj, ns, D["seed"], D["offset"], D["n"], None, D["mu"], D["sigma"], got[rj][0],
+                         nb.NRNG_F32, main, got[rj][1])
+    torch.cuda.synchronize()
+    assert torch.equal(got[rj][0], ref[rj][0])
