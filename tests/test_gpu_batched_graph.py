@@ -290,19 +290,20 @@ def test_polar_dev_under_torch_graph_capture():
                                     nb.NRNG_METHOD_B3, nb.NRNG_METHOD_R, nb.NRNG_METHOD_B2])
 def test_exec_parts_equal_exec(method):
     """The count half then the generate half of the exec sequence, and the
-    exec whose main kernel is timed by two events (the timing hooks), give
-    exactly what exec gives; the events bracket a positive time no longer
-    than the whole exec's; a part outside 0..2 is an argument error."""
+    exec whose main kernel is timed by two events (the timing hooks, whole
+    or as the generate half after the count half), give exactly what exec
+    gives; the events bracket a positive time no longer than the whole
+    exec's; a part outside 0..2 is an argument error."""
     d = dev()
     cfg = small_config(61)
     D = to_dev(cfg, d)
     ns = len(cfg["n"])
     stream = torch.cuda.current_stream()
-    evs = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
     for e in evs:
         e.record(stream)   # torch creates its events on their first record
     outs = []
-    for parts in ((0,), (1, 2), ("timed",)):
+    for parts in ((0,), (1, 2), (1, "timed2"), ("timed",)):
         out = torch.full((cfg["total"],), float("nan"), dtype=torch.float32, device=d)
         cons = torch.zeros(ns, dtype=torch.int64, device=d)
         case("exec parts", method, parts)
@@ -313,6 +314,9 @@ def test_exec_parts_equal_exec(method):
                 nb.nrng_batched_exec_timed(0, method, ns, D["seed"], D["offset"], D["n"], None, D["mu"], D["sigma"],
                                            out, nb.NRNG_F32, stream, cons, evs[1], evs[2])
                 evs[3].record(stream)
+            elif p == "timed2":
+                nb.nrng_batched_exec_timed(2, method, ns, D["seed"], D["offset"], D["n"], None, D["mu"],
+                                           D["sigma"], out, nb.NRNG_F32, stream, cons, evs[4], evs[5])
             else:
                 nb.nrng_batched_exec_part(p, method, ns, D["seed"], D["offset"], D["n"], None, D["mu"],
                                           D["sigma"], out, nb.NRNG_F32, None, cons)
@@ -323,6 +327,7 @@ def test_exec_parts_equal_exec(method):
         assert np.array_equal(outs[0][1], o[1])
     kernel_ms, exec_ms = evs[1].elapsed_time(evs[2]), evs[0].elapsed_time(evs[3])
     assert 0.0 < kernel_ms <= exec_ms, (kernel_ms, exec_ms)
+    assert evs[4].elapsed_time(evs[5]) > 0.0
     with pytest.raises(nb.NrngError):
         nb.nrng_batched_exec_part(3, method, ns, D["seed"], D["offset"], D["n"], None, D["mu"], D["sigma"],
                                   outs[0][0], nb.NRNG_F32, None, None)
