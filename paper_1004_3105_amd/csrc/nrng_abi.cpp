@@ -739,9 +739,9 @@ int nrng_batched_exec(int method, uint32_t nstreams, const uint64_t *d_seed, con
                                   stream, d_consumed);
 }
 
-// exec over the latest plan: part 0 = the whole launch sequence, 1 = the
-// count kernels, 2 = the main kernel; ev0 / ev1 (may be null) record the
-// main kernel's own start and end.
+// exec over the latest plan of the method's family: part 0 = the whole
+// launch sequence, 1 = the count kernels, 2 = the main kernel; ev0 / ev1
+// (may be null) record the main kernel's own start and end.
 static int batched_exec(int part, int method, uint32_t nstreams, const uint64_t *d_seed, const uint64_t *d_offset,
                         const uint64_t *d_n, const uint64_t *d_out_off, const double *d_mu, const double *d_sigma,
                         void *out, int dtype, void *stream, uint64_t *d_consumed, hipEvent_t ev0, hipEvent_t ev1)
