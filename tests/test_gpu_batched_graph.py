@@ -474,3 +474,49 @@ def test_two_families_planned_together_and_run_side_by_side(pair):
                          nb.NRNG_F32, main, got[rj][1])
     torch.cuda.synchronize()
     assert torch.equal(got[rj][0], ref[rj][0])
+
+
+def test_exec_needs_the_matching_plan_of_its_family():
+    """exec runs over the latest plan of its method's family and returns
+    NRNG_EINVAL, before any launch, unless that plan was made for the same
+    method, stream count, dtype and layout; a plan of the other family
+    leaves it in place."""
+    d = dev()
+    cfg = small_config(37)
+    D = to_dev(cfg, d)
+    ns, total = len(cfg["n"]), cfg["total"]
+    off = torch.from_numpy(cfg["out_off"].view(np.int64)).to(d)
+    out = torch.full((total,), float("nan"), dtype=torch.float32, device=d)
+    out64 = torch.full((total,), float("nan"), dtype=torch.float64, device=d)
+    cons = torch.zeros(ns, dtype=torch.int64, device=d)
+
+    def exec_status(method, nstreams=ns, d_out_off=None, o=out, dtype=nb.NRNG_F32):
+        try:
+            nb.nrng_batched_exec(method, nstreams, D["seed"], D["offset"], D["n"], d_out_off, D["mu"], D["sigma"],
+                                 o, dtype, None, cons)
+        except nb.NrngError as e:
+            return e.status
+        return nb.NRNG_OK
+
+    case("plan of the family", "B1 then B3")
+    nb.nrng_batched_plan(nb.NRNG_METHOD_B1, ns, D["n"], None, total, nb.NRNG_F32, None, cons)
+    nb.nrng_batched_plan(nb.NRNG_METHOD_B3, ns, D["n"], None, total, nb.NRNG_F32, None, cons)
+    assert exec_status(nb.NRNG_METHOD_B1) == nb.NRNG_EINVAL
+    assert exec_status(nb.NRNG_METHOD_B3) == nb.NRNG_OK
+    case("plan of the family", "Polar: stream count, dtype, layout")
+    nb.nrng_batched_plan(nb.NRNG_METHOD_POLAR, ns, D["n"], None, total, nb.NRNG_F32, None, cons)
+    assert exec_status(nb.NRNG_METHOD_P2) == nb.NRNG_EINVAL
+    assert exec_status(nb.NRNG_METHOD_POLAR, nstreams=ns - 1) == nb.NRNG_EINVAL
+    assert exec_status(nb.NRNG_METHOD_POLAR, o=out64, dtype=nb.NRNG_F64) == nb.NRNG_EINVAL
+    assert exec_status(nb.NRNG_METHOD_POLAR, d_out_off=off) == nb.NRNG_EINVAL
+    case("plan of the family", "B2 plan leaves the Polar plan")
+    nb.nrng_batched_plan(nb.NRNG_METHOD_B2, ns, D["n"], None, total, nb.NRNG_F32, None, cons)
+    assert exec_status(nb.NRNG_METHOD_POLAR) == nb.NRNG_OK
+    torch.cuda.synchronize()
+    ref = torch.full((total,), float("nan"), dtype=torch.float32, device=d)
+    ref_cons = torch.zeros(ns, dtype=torch.int64, device=d)
+    nb.nrng_batched(nb.NRNG_METHOD_POLAR, ns, D["seed"], D["offset"], D["n"], None, D["mu"], D["sigma"], ref, total,
+                    nb.NRNG_F32, None, ref_cons)
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref)
+    assert np.array_equal(u64(cons), u64(ref_cons))
